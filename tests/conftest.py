@@ -1,0 +1,23 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: long CPU-only oracle runs")
+
+
+def pytest_collection_modifyitems(config, items):
+    # slow oracle runs are opt-in (NPHASE_SLOW=1) so the CPU suite stays at a few minutes
+    if os.environ.get("NPHASE_SLOW") == "1":
+        return
+    skip = pytest.mark.skip(reason="slow oracle run; set NPHASE_SLOW=1")
+    for it in items:
+        if "slow" in it.keywords:
+            it.add_marker(skip)
