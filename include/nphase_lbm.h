@@ -1,0 +1,144 @@
+/*
+ * nphase_lbm.h -- C ABI of the MI355X (gfx950) N-phase conservative Allen-Cahn +
+ * Navier-Stokes lattice Boltzmann library (libnphase_lbm.so).
+ *
+ * The method is the consistent and conservative MRT lattice Boltzmann scheme of
+ * Zhan, Liu, Chai and Shi for immiscible N-phase flow:
+ *   - N-1 (or N) phase-field distribution sets f_{i,p} with the conservative Allen-Cahn
+ *     source of Model A (Lagrange multiplier with exponent n, Sec. 2.1 Eq. eq-source1) or
+ *     Model B (pairwise normals, Sec. 2.1 Eq. eq-source2), relaxed in moment space
+ *     (Sec. 3 first evolution equation; Sec. 4 intro: natural M, diagonal S, s1 = 1/tau_f);
+ *   - one hydrodynamic set g_i with the potential-form surface tension (Sec. 2.2,
+ *     Eq. eq-Fs1), the consistent mass flux m = rho u + m_phi and the correction force
+ *     F_c = -div(m_phi u - u m_phi)/2 (Sec. 3 second evolution equation);
+ *   - isotropic lattice-weight gradient/Laplacian stencils, lagged velocity in the force
+ *     and explicit Euler time derivatives (Sec. 3 closing paragraph).
+ * Lattices: D2Q9 (the paper's) and D3Q19 (raw-moment basis built the same way).
+ * Boundaries: periodic in every direction.
+ *
+ * Conventions
+ *   - Every function returns an int status: NPHASE_OK (0) or a negative error code.
+ *     Nothing throws across the ABI.
+ *   - Device pointers are HIP device addresses on the device that was current when the
+ *     handle was created.  Host pointers are marked _host.
+ *   - All device work is enqueued on the stream given at create (a hipStream_t passed as
+ *     void*; NULL = the legacy default stream).  Only the functions documented as
+ *     synchronising wait for the device.
+ *   - Grid fields are stored x fastest: index = x + nx*(y + ny*z).  A field with
+ *     components (phases p or vector components a) is [component][z][y][x].
+ *   - The library never allocates device memory for the state: the caller passes a
+ *     workspace of nphase_lbm_workspace_bytes() bytes (256-byte aligned) and keeps it
+ *     alive until nphase_lbm_destroy.  The only allocation the library makes is the host
+ *     handle itself.
+ *   - A HIP error puts the handle into a failed state: that call returns NPHASE_EDEVICE
+ *     and every later call except last_error/destroy returns NPHASE_ESTATE.
+ */
+#ifndef NPHASE_LBM_H
+#define NPHASE_LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  NPHASE_OK = 0,
+  NPHASE_EINVAL = -1,   /* invalid argument or parameter set (checked on the host)      */
+  NPHASE_ENOMEM = -2,   /* workspace or caller buffer too small                         */
+  NPHASE_EDEVICE = -3,  /* a HIP call failed                                            */
+  NPHASE_ENAN = -4,     /* non-finite values found by nphase_lbm_check                  */
+  NPHASE_ESTATE = -5,   /* handle in a failed state, or not initialised                 */
+  NPHASE_ENOTSUP = -6   /* valid parameters outside what this build supports            */
+};
+
+enum { NPHASE_D2Q9 = 0, NPHASE_D3Q19 = 1 };
+enum { NPHASE_MODEL_A = 0, NPHASE_MODEL_B = 1 };
+/* NPHASE_FP64: the plain method in double precision.
+ * NPHASE_FP32: populations stored in single precision as deviations from the rest
+ *   weights of the previous-step local order parameter (f~_i = f_i - w_i phi^{t-1}), FP32
+ *   arithmetic; the initial equilibrium set-up and the per-phase mass reductions are FP64. */
+enum { NPHASE_FP64 = 0, NPHASE_FP32 = 1 };
+
+#define NPHASE_MAX_N 8 /* size of the parameter arrays; this build evolves N in [2, 6] */
+
+typedef struct nphase_lbm_s *nphase_lbm_t;
+
+/* Statement of the problem (Sec. 2-3).  Lattice units: dx = dt = 1, c_s^2 = 1/3. */
+typedef struct {
+  int32_t struct_size;   /* = sizeof(nphase_lbm_params) (ABI check)                       */
+  int32_t lattice;       /* NPHASE_D2Q9 | NPHASE_D3Q19                                    */
+  int32_t nx, ny, nz;    /* grid; nz = 1 for D2Q9; every extent >= 1                      */
+  int32_t n_phases;      /* N, 2..6 in this build                                         */
+  int32_t model;         /* NPHASE_MODEL_A | NPHASE_MODEL_B                               */
+  int32_t model_a_n;     /* Model A exponent n (integer >= 1, Sec. 2.1); ignored for B    */
+  int32_t precision;     /* NPHASE_FP64 | NPHASE_FP32                                     */
+  int32_t solve_all;     /* 0: evolve phases 0..N-2, phase N-1 = 1 - sum (Sec. 4 intro);
+                            1: evolve all N sets                                          */
+  double sigma[NPHASE_MAX_N * NPHASE_MAX_N]; /* row-major N x N pair surface tensions:
+                            symmetric, zero diagonal, > 0 off the diagonal (Sec. 2.2)     */
+  double rho[NPHASE_MAX_N];   /* phase densities rho_p > 0 (Sec. 2.2, Eq. eq-rho)         */
+  double tau_g[NPHASE_MAX_N]; /* per-phase fluid relaxation times > 1/2; phase viscosity
+                            mu_p = rho_p (tau_g,p - 1/2) c_s^2 (Sec. 3); the local tau_g
+                            follows from the mixed mu and rho                              */
+  double mobility;       /* M > 0; phase-field relaxation tau_f = 1/2 + M / c_s^2 (Sec. 3) */
+  double eps;            /* interface thickness epsilon > 0 (Sec. 2.1)                     */
+  double gravity[3];     /* body force (rho - rho_bar) g, rho_bar = mean density at t = 0 */
+} nphase_lbm_params;
+
+/* Bytes of device workspace for this parameter set. */
+int nphase_lbm_workspace_bytes(const nphase_lbm_params *params, size_t *bytes_host);
+
+/* Validate and copy the parameters, carve the caller's workspace and bind the stream.
+ * Errors: EINVAL (bad parameters, NULL pointers, misaligned workspace), ENOMEM
+ * (ws_bytes too small), ENOTSUP (N outside 2..6).  No device work is done. */
+int nphase_lbm_create(const nphase_lbm_params *params, void *workspace_dev, size_t ws_bytes,
+                      void *hip_stream, nphase_lbm_t *out_host);
+
+/* Initial state from the N order parameters phi0 [N][nz][ny][nx] (FP64, device):
+ * f = f^eq(phi0, u = 0), g = g^eq(P = 0, u = 0), u^{-1} = 0, phi^{-1} = phi0,
+ * m_phi^{-1} = 0 (the paper leaves the start silent; this is the equilibrium at rest).
+ * With solve_all = 0 the last phase is rebuilt as 1 - sum of the others.  Computes the
+ * FP64 mean density used by gravity.  Synchronises the stream. */
+int nphase_lbm_init(nphase_lbm_t h, const double *phi0_dev);
+
+/* Advance nsteps >= 0 time steps: one fused kernel per step (populations pulled from one
+ * buffer, collided, pushed to the other).  Asynchronous on the stream. */
+int nphase_lbm_step(nphase_lbm_t h, int64_t nsteps);
+
+/* Macroscopic fields at the current time T without changing the state (FP64, device):
+ * phi [N][nz][ny][nx], u [d][nz][ny][nx], P [nz][ny][nx]; a NULL pointer skips that field.
+ * u^T is the velocity the next step computes (Sec. 3 macroscopic recovery).  Async. */
+int nphase_lbm_fields(nphase_lbm_t h, double *phi_dev, double *u_dev, double *p_dev);
+
+/* Per-phase mass sum_x phi_p for all N phases, FP64, deterministic reduction order.
+ * Writes N doubles to mass_host.  Synchronises the stream. */
+int nphase_lbm_mass(nphase_lbm_t h, double *mass_host);
+
+/* all_finite_host = 1 if every phi^{t-1} and u value of the state is finite, else 0
+ * and the call returns NPHASE_ENAN.  Synchronises the stream. */
+int nphase_lbm_check(nphase_lbm_t h, int *all_finite_host);
+
+/* Number of completed time steps since init. */
+int nphase_lbm_time(nphase_lbm_t h, int64_t *t_host);
+
+/* Full state (populations, history fields, step parity and time) for checkpointing:
+ * save copies it into a caller device buffer of state_bytes bytes, load restores it.
+ * Async. */
+int nphase_lbm_state_bytes(nphase_lbm_t h, size_t *bytes_host);
+int nphase_lbm_save_state(nphase_lbm_t h, void *state_dev);
+int nphase_lbm_load_state(nphase_lbm_t h, const void *state_dev);
+
+/* Message of the last error on this handle (never NULL), and the name of a status code. */
+const char *nphase_lbm_last_error(nphase_lbm_t h);
+const char *nphase_lbm_strerror(int status);
+
+/* Release the handle (does not touch the caller's workspace).  NULL is accepted. */
+int nphase_lbm_destroy(nphase_lbm_t h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NPHASE_LBM_H */

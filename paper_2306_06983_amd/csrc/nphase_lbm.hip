@@ -1,0 +1,485 @@
+// Host side of the C ABI declared in include/nphase_lbm.h: parameter validation, the
+// derived coefficients of the method (beta_pq, k_pq, tau_f, mu_p), workspace carving,
+// launches on the caller's stream, mass / finite reductions and state copies.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/nphase_lbm.h"
+#include "aux_kernels.hpp"
+#include "dispatch.hpp"
+
+using namespace nphase;
+
+struct nphase_lbm_s {
+  nphase_lbm_params prm;
+  int N = 0, NS = 0, D = 0, Q = 0, lat = 0, prec = 0;
+  long long V = 0;
+  size_t tsize = 8;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  void* f[2] = {nullptr, nullptr};
+  void* g[2] = {nullptr, nullptr};
+  void* u[2] = {nullptr, nullptr};
+  void* pm[2] = {nullptr, nullptr};
+  void* mm = nullptr;
+  double* partial = nullptr;
+  double* mass_dev = nullptr;
+  int* flag_dev = nullptr;
+  int cur = 0;
+  int64_t t = 0;
+  double rho_bar = 0.0;
+  int ntx = 0, nty = 0, ntz = 0, ntiles = 0;
+  bool inited = false;
+  bool failed = false;
+  std::string err;
+  StepArgs<double> a64[2];
+  StepArgs<float> a32[2];
+};
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr double CS2 = 1.0 / 3.0;
+
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Layout {
+  size_t f, g, u, pm, mm, partial, mass, flag, total;
+};
+
+// sizes of every buffer for a validated parameter set
+Layout layout_of(const nphase_lbm_params& p) {
+  const int D = p.lattice == NPHASE_D2Q9 ? 2 : 3;
+  const int Q = p.lattice == NPHASE_D2Q9 ? 9 : 19;
+  const int N = p.n_phases;
+  const int NS = p.solve_all ? N : N - 1;
+  const size_t V = (size_t)p.nx * (size_t)p.ny * (size_t)p.nz;
+  const size_t ts = p.precision == NPHASE_FP64 ? 8 : 4;
+  Layout L;
+  L.f = align_up((size_t)NS * Q * V * ts);
+  L.g = align_up((size_t)(Q - 1) * V * ts);
+  L.u = align_up((size_t)D * V * ts);
+  L.pm = align_up((size_t)NS * V * ts);
+  L.mm = align_up((size_t)D * V * ts);
+  L.partial = align_up((size_t)MAXN * RED_BLOCKS * sizeof(double));
+  L.mass = align_up(MAXN * sizeof(double));
+  L.flag = align_up(sizeof(int) * 4);
+  L.total = 2 * (L.f + L.g + L.u + L.pm) + L.mm + L.partial + L.mass + L.flag;
+  return L;
+}
+
+int validate(const nphase_lbm_params* p, std::string* why) {
+  auto bad = [&](const char* m) {
+    if (why) *why = m;
+    return NPHASE_EINVAL;
+  };
+  if (!p) return bad("params is NULL");
+  if (p->struct_size != (int32_t)sizeof(nphase_lbm_params)) return bad("struct_size mismatch");
+  if (p->lattice != NPHASE_D2Q9 && p->lattice != NPHASE_D3Q19) return bad("unknown lattice");
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return bad("grid extents must be >= 1");
+  if (p->lattice == NPHASE_D2Q9 && p->nz != 1) return bad("D2Q9 needs nz = 1");
+  if ((double)p->nx * p->ny * p->nz > 4.0e9) return bad("grid too large");
+  if (p->n_phases < 2 || p->n_phases > NPHASE_MAX_N) return bad("n_phases out of [2, 8]");
+  if (p->model != NPHASE_MODEL_A && p->model != NPHASE_MODEL_B) return bad("unknown model");
+  if (p->model == NPHASE_MODEL_A && p->model_a_n < 1) return bad("model_a_n must be >= 1");
+  if (p->precision != NPHASE_FP64 && p->precision != NPHASE_FP32) return bad("unknown precision");
+  if (p->solve_all != 0 && p->solve_all != 1) return bad("solve_all must be 0 or 1");
+  const int N = p->n_phases;
+  for (int i = 0; i < N; ++i) {
+    if (!(p->sigma[i * NPHASE_MAX_N + i] == 0.0)) return bad("sigma_pp must be 0");
+    for (int j = 0; j < N; ++j) {
+      const double s = p->sigma[i * NPHASE_MAX_N + j];
+      if (!std::isfinite(s)) return bad("sigma not finite");
+      if (i != j && !(s > 0.0)) return bad("sigma_pq must be > 0");
+      if (s != p->sigma[j * NPHASE_MAX_N + i]) return bad("sigma must be symmetric");
+    }
+    if (!(p->rho[i] > 0.0) || !std::isfinite(p->rho[i])) return bad("rho_p must be > 0");
+    if (!(p->tau_g[i] > 0.5) || !std::isfinite(p->tau_g[i])) return bad("tau_g,p must be > 1/2");
+  }
+  if (!(p->mobility > 0.0) || !std::isfinite(p->mobility)) return bad("mobility must be > 0");
+  if (!(p->eps > 0.0) || !std::isfinite(p->eps)) return bad("eps must be > 0");
+  for (int d = 0; d < 3; ++d)
+    if (!std::isfinite(p->gravity[d])) return bad("gravity not finite");
+  if (N < NMIN || N > NMAX) {
+    if (why) *why = "n_phases outside the instantiated range [2, 6]";
+    return NPHASE_ENOTSUP;
+  }
+  return NPHASE_OK;
+}
+
+int fail_hip(nphase_lbm_t h, hipError_t e, const char* where) {
+  h->failed = true;
+  h->err = std::string(where) + ": " + hipGetErrorString(e);
+  return NPHASE_EDEVICE;
+}
+
+#define HIPCHK(call, where)                          \
+  do {                                               \
+    hipError_t e_ = (call);                          \
+    if (e_ != hipSuccess) return fail_hip(h, e_, where); \
+  } while (0)
+
+template <typename T>
+void fill_args(nphase_lbm_t h, StepArgs<T>* out) {
+  const nphase_lbm_params& p = h->prm;
+  for (int side = 0; side < 2; ++side) {
+    StepArgs<T>& a = out[side];
+    std::memset(&a, 0, sizeof(a));
+    const int dst = 1 - side;
+    a.f_src = (const T*)h->f[side];
+    a.f_dst = (T*)h->f[dst];
+    a.g_src = (const T*)h->g[side];
+    a.g_dst = (T*)h->g[dst];
+    a.u_src = (const T*)h->u[side];
+    a.u_dst = (T*)h->u[dst];
+    a.pm_src = (const T*)h->pm[side];
+    a.pm_dst = (T*)h->pm[dst];
+    a.mm = (T*)h->mm;
+    a.nx = p.nx;
+    a.ny = p.ny;
+    a.nz = p.nz;
+    a.ntx = h->ntx;
+    a.nty = h->nty;
+    a.ntz = h->ntz;
+    a.ntiles = h->ntiles;
+    a.V = h->V;
+    a.model_a_n = p.model_a_n;
+    for (int i = 0; i < h->N; ++i) {
+      a.rho[i] = (T)p.rho[i];
+      // mu_p = rho_p (tau_g,p - 1/2) c_s^2  (Sec. 3)
+      a.mu[i] = (T)(p.rho[i] * (p.tau_g[i] - 0.5) * CS2);
+      for (int j = 0; j < h->N; ++j) {
+        const double s = p.sigma[i * NPHASE_MAX_N + j];
+        a.beta2[i * MAXN + j] = (T)(2.0 * 3.0 * s / p.eps);   // 2 beta_pq, beta = 3 sigma/eps
+        a.kappa[i * MAXN + j] = (T)(-0.75 * p.eps * s);       // k_pq = -3 eps sigma / 4
+      }
+    }
+    a.mob = (T)p.mobility;
+    a.s1 = (T)(1.0 / (0.5 + p.mobility / CS2));   // M = (tau_f - 1/2) c_s^2
+    a.four_over_eps = (T)(4.0 / p.eps);
+    a.rho_bar = (T)h->rho_bar;
+    for (int d = 0; d < 3; ++d) a.grav[d] = (T)p.gravity[d];
+  }
+}
+
+void refresh_args(nphase_lbm_t h) {
+  if (h->prec == NPHASE_FP64) fill_args<double>(h, h->a64);
+  else fill_args<float>(h, h->a32);
+}
+
+hipError_t launch(nphase_lbm_t h, int mode, int side) {
+  const int N = h->N, sa = h->prm.solve_all, model = h->prm.model;
+  if (h->prec == NPHASE_FP64) {
+    if (h->lat == NPHASE_D2Q9)
+      return launch_step<double, LAT_D2Q9>(N, sa, model, mode, h->a64[side], h->ntiles, h->stream);
+    return launch_step<double, LAT_D3Q19>(N, sa, model, mode, h->a64[side], h->ntiles, h->stream);
+  }
+  if (h->lat == NPHASE_D2Q9)
+    return launch_step<float, LAT_D2Q9>(N, sa, model, mode, h->a32[side], h->ntiles, h->stream);
+  return launch_step<float, LAT_D3Q19>(N, sa, model, mode, h->a32[side], h->ntiles, h->stream);
+}
+
+template <typename T, int LAT>
+hipError_t launch_mass(nphase_lbm_t h) {
+  long long nb = (h->V + 255) / 256;
+  const int nblk = (int)(nb < RED_BLOCKS ? nb : RED_BLOCKS);
+  hipLaunchKernelGGL((mass_partial_kernel<T, LAT>), dim3(nblk), dim3(256), 0, h->stream,
+                     (const T*)h->f[h->cur], (const T*)h->pm[h->cur], h->partial, h->N, h->NS,
+                     h->V);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(mass_final_kernel, dim3(h->N), dim3(256), 0, h->stream,
+                     (const double*)h->partial, h->mass_dev, nblk);
+  return hipGetLastError();
+}
+
+hipError_t mass_async(nphase_lbm_t h) {
+  if (h->prec == NPHASE_FP64)
+    return h->lat == NPHASE_D2Q9 ? launch_mass<double, LAT_D2Q9>(h) : launch_mass<double, LAT_D3Q19>(h);
+  return h->lat == NPHASE_D2Q9 ? launch_mass<float, LAT_D2Q9>(h) : launch_mass<float, LAT_D3Q19>(h);
+}
+
+template <typename T, int LAT>
+hipError_t launch_init(nphase_lbm_t h, const double* phi0) {
+  const int nb = (int)((h->V + 255) / 256);
+  const int s = h->cur;
+  hipLaunchKernelGGL((init_kernel<T, LAT>), dim3(nb), dim3(256), 0, h->stream, phi0, (T*)h->f[s],
+                     (T*)h->g[s], (T*)h->u[s], (T*)h->pm[s], (T*)h->mm, h->NS, h->V);
+  return hipGetLastError();
+}
+
+int check_handle(nphase_lbm_t h) {
+  if (!h) return NPHASE_EINVAL;
+  if (h->failed) return NPHASE_ESTATE;
+  return NPHASE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nphase_lbm_workspace_bytes(const nphase_lbm_params* params, size_t* bytes_host) {
+  if (!bytes_host) return NPHASE_EINVAL;
+  const int rc = validate(params, nullptr);
+  if (rc != NPHASE_OK) return rc;
+  *bytes_host = layout_of(*params).total;
+  return NPHASE_OK;
+}
+
+int nphase_lbm_create(const nphase_lbm_params* params, void* workspace_dev, size_t ws_bytes,
+                      void* hip_stream, nphase_lbm_t* out_host) {
+  if (!out_host) return NPHASE_EINVAL;
+  *out_host = nullptr;
+  const int rc = validate(params, nullptr);
+  if (rc != NPHASE_OK) return rc;
+  if (!workspace_dev || ((uintptr_t)workspace_dev % ALIGN) != 0) return NPHASE_EINVAL;
+  const Layout L = layout_of(*params);
+  if (ws_bytes < L.total) return NPHASE_ENOMEM;
+  nphase_lbm_t h = new (std::nothrow) nphase_lbm_s();
+  if (!h) return NPHASE_ENOMEM;
+  h->prm = *params;
+  h->N = params->n_phases;
+  h->NS = params->solve_all ? h->N : h->N - 1;
+  h->lat = params->lattice;
+  h->D = h->lat == NPHASE_D2Q9 ? 2 : 3;
+  h->Q = h->lat == NPHASE_D2Q9 ? 9 : 19;
+  h->prec = params->precision;
+  h->tsize = h->prec == NPHASE_FP64 ? 8 : 4;
+  h->V = (long long)params->nx * params->ny * params->nz;
+  h->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&h->device) != hipSuccess) h->device = 0;
+  h->ws = (char*)workspace_dev;
+  h->ws_bytes = ws_bytes;
+  char* q = h->ws;
+  for (int s = 0; s < 2; ++s) { h->f[s] = q; q += L.f; }
+  for (int s = 0; s < 2; ++s) { h->g[s] = q; q += L.g; }
+  for (int s = 0; s < 2; ++s) { h->u[s] = q; q += L.u; }
+  for (int s = 0; s < 2; ++s) { h->pm[s] = q; q += L.pm; }
+  h->mm = q; q += L.mm;
+  h->partial = (double*)q; q += L.partial;
+  h->mass_dev = (double*)q; q += L.mass;
+  h->flag_dev = (int*)q; q += L.flag;
+  int TX, TY, TZ;
+  if (h->lat == NPHASE_D2Q9) {
+    TX = TileShape<LAT_D2Q9>::TX; TY = TileShape<LAT_D2Q9>::TY; TZ = 1;
+  } else {
+    TX = TileShape<LAT_D3Q19>::TX; TY = TileShape<LAT_D3Q19>::TY; TZ = TileShape<LAT_D3Q19>::TZ;
+  }
+  h->ntx = (params->nx + TX - 1) / TX;
+  h->nty = (params->ny + TY - 1) / TY;
+  h->ntz = (params->nz + TZ - 1) / TZ;
+  h->ntiles = h->ntx * h->nty * h->ntz;
+  refresh_args(h);
+  *out_host = h;
+  return NPHASE_OK;
+}
+
+int nphase_lbm_init(nphase_lbm_t h, const double* phi0_dev) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!phi0_dev) { h->err = "phi0 is NULL"; return NPHASE_EINVAL; }
+  h->cur = 0;
+  h->t = 0;
+  hipError_t e;
+  if (h->prec == NPHASE_FP64)
+    e = h->lat == NPHASE_D2Q9 ? launch_init<double, LAT_D2Q9>(h, phi0_dev) : launch_init<double, LAT_D3Q19>(h, phi0_dev);
+  else
+    e = h->lat == NPHASE_D2Q9 ? launch_init<float, LAT_D2Q9>(h, phi0_dev) : launch_init<float, LAT_D3Q19>(h, phi0_dev);
+  HIPCHK(e, "init kernel");
+  HIPCHK(mass_async(h), "mass kernel");
+  double mass[MAXN];
+  HIPCHK(hipMemcpyAsync(mass, h->mass_dev, sizeof(double) * h->N, hipMemcpyDeviceToHost, h->stream), "mass copy");
+  HIPCHK(hipStreamSynchronize(h->stream), "init sync");
+  double rb = 0.0;
+  for (int p = 0; p < h->N; ++p) rb += h->prm.rho[p] * mass[p];
+  h->rho_bar = rb / (double)h->V;
+  refresh_args(h);
+  h->inited = true;
+  return NPHASE_OK;
+}
+
+int nphase_lbm_step(nphase_lbm_t h, int64_t nsteps) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!h->inited) { h->err = "step before init"; return NPHASE_ESTATE; }
+  if (nsteps < 0) { h->err = "nsteps < 0"; return NPHASE_EINVAL; }
+  for (int64_t k = 0; k < nsteps; ++k) {
+    HIPCHK(launch(h, MODE_STEP, h->cur), "step kernel");
+    h->cur ^= 1;
+    h->t += 1;
+  }
+  return NPHASE_OK;
+}
+
+int nphase_lbm_fields(nphase_lbm_t h, double* phi_dev, double* u_dev, double* p_dev) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!h->inited) { h->err = "fields before init"; return NPHASE_ESTATE; }
+  if (!phi_dev && !u_dev && !p_dev) return NPHASE_OK;
+  double* sphi = phi_dev;
+  double* su = u_dev;
+  double* sp = p_dev;
+  if (h->prec == NPHASE_FP64) {
+    StepArgs<double> a = h->a64[h->cur];
+    a.phi_out = sphi; a.u_out = su; a.p_out = sp;
+    a.f_dst = nullptr; a.g_dst = nullptr; a.u_dst = nullptr; a.pm_dst = nullptr;
+    const int N = h->N, sa = h->prm.solve_all, model = h->prm.model;
+    hipError_t e = h->lat == NPHASE_D2Q9
+                       ? launch_step<double, LAT_D2Q9>(N, sa, model, MODE_FIELDS, a, h->ntiles, h->stream)
+                       : launch_step<double, LAT_D3Q19>(N, sa, model, MODE_FIELDS, a, h->ntiles, h->stream);
+    HIPCHK(e, "fields kernel");
+  } else {
+    StepArgs<float> a = h->a32[h->cur];
+    a.phi_out = sphi; a.u_out = su; a.p_out = sp;
+    a.f_dst = nullptr; a.g_dst = nullptr; a.u_dst = nullptr; a.pm_dst = nullptr;
+    const int N = h->N, sa = h->prm.solve_all, model = h->prm.model;
+    hipError_t e = h->lat == NPHASE_D2Q9
+                       ? launch_step<float, LAT_D2Q9>(N, sa, model, MODE_FIELDS, a, h->ntiles, h->stream)
+                       : launch_step<float, LAT_D3Q19>(N, sa, model, MODE_FIELDS, a, h->ntiles, h->stream);
+    HIPCHK(e, "fields kernel");
+  }
+  return NPHASE_OK;
+}
+
+int nphase_lbm_mass(nphase_lbm_t h, double* mass_host) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!mass_host) { h->err = "mass_host is NULL"; return NPHASE_EINVAL; }
+  if (!h->inited) { h->err = "mass before init"; return NPHASE_ESTATE; }
+  HIPCHK(mass_async(h), "mass kernel");
+  HIPCHK(hipMemcpyAsync(mass_host, h->mass_dev, sizeof(double) * h->N, hipMemcpyDeviceToHost, h->stream), "mass copy");
+  HIPCHK(hipStreamSynchronize(h->stream), "mass sync");
+  return NPHASE_OK;
+}
+
+int nphase_lbm_check(nphase_lbm_t h, int* all_finite_host) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!all_finite_host) { h->err = "all_finite_host is NULL"; return NPHASE_EINVAL; }
+  if (!h->inited) { h->err = "check before init"; return NPHASE_ESTATE; }
+  hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, h->stream, h->flag_dev, 1);
+  HIPCHK(hipGetLastError(), "zero kernel");
+  const long long n_u = (long long)h->D * h->V, n_pm = (long long)h->NS * h->V;
+  const int nb = 1024;
+  if (h->prec == NPHASE_FP64) {
+    hipLaunchKernelGGL(finite_kernel<double>, dim3(nb), dim3(256), 0, h->stream, (const double*)h->u[h->cur], n_u, h->flag_dev);
+    hipLaunchKernelGGL(finite_kernel<double>, dim3(nb), dim3(256), 0, h->stream, (const double*)h->pm[h->cur], n_pm, h->flag_dev);
+  } else {
+    hipLaunchKernelGGL(finite_kernel<float>, dim3(nb), dim3(256), 0, h->stream, (const float*)h->u[h->cur], n_u, h->flag_dev);
+    hipLaunchKernelGGL(finite_kernel<float>, dim3(nb), dim3(256), 0, h->stream, (const float*)h->pm[h->cur], n_pm, h->flag_dev);
+  }
+  HIPCHK(hipGetLastError(), "finite kernel");
+  int flag = 0;
+  HIPCHK(hipMemcpyAsync(&flag, h->flag_dev, sizeof(int), hipMemcpyDeviceToHost, h->stream), "flag copy");
+  HIPCHK(hipStreamSynchronize(h->stream), "check sync");
+  *all_finite_host = flag ? 0 : 1;
+  if (flag) { h->err = "non-finite values in the state"; return NPHASE_ENAN; }
+  return NPHASE_OK;
+}
+
+int nphase_lbm_time(nphase_lbm_t h, int64_t* t_host) {
+  if (!h || !t_host) return NPHASE_EINVAL;
+  *t_host = h->t;
+  return NPHASE_OK;
+}
+
+static size_t state_payload(nphase_lbm_t h, size_t* parts) {
+  const size_t ts = h->tsize;
+  parts[0] = (size_t)h->NS * h->Q * h->V * ts;
+  parts[1] = (size_t)(h->Q - 1) * h->V * ts;
+  parts[2] = (size_t)h->D * h->V * ts;
+  parts[3] = (size_t)h->NS * h->V * ts;
+  parts[4] = (size_t)h->D * h->V * ts;
+  return parts[0] + parts[1] + parts[2] + parts[3] + parts[4];
+}
+
+int nphase_lbm_state_bytes(nphase_lbm_t h, size_t* bytes_host) {
+  if (!h || !bytes_host) return NPHASE_EINVAL;
+  size_t parts[5];
+  *bytes_host = ALIGN + state_payload(h, parts);
+  return NPHASE_OK;
+}
+
+struct StateHeader {
+  int64_t t;
+  double rho_bar;
+  int64_t magic;
+};
+
+int nphase_lbm_save_state(nphase_lbm_t h, void* state_dev) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!state_dev) { h->err = "state buffer is NULL"; return NPHASE_EINVAL; }
+  if (!h->inited) { h->err = "save before init"; return NPHASE_ESTATE; }
+  size_t parts[5];
+  state_payload(h, parts);
+  static thread_local StateHeader hdr;
+  hdr.t = h->t;
+  hdr.rho_bar = h->rho_bar;
+  hdr.magic = 0x4e5048415345;
+  char* q = (char*)state_dev;
+  HIPCHK(hipMemcpyAsync(q, &hdr, sizeof(hdr), hipMemcpyHostToDevice, h->stream), "save header");
+  HIPCHK(hipStreamSynchronize(h->stream), "save header sync");
+  q += ALIGN;
+  const void* src[5] = {h->f[h->cur], h->g[h->cur], h->u[h->cur], h->pm[h->cur], h->mm};
+  for (int k = 0; k < 5; ++k) {
+    HIPCHK(hipMemcpyAsync(q, src[k], parts[k], hipMemcpyDeviceToDevice, h->stream), "save copy");
+    q += parts[k];
+  }
+  return NPHASE_OK;
+}
+
+int nphase_lbm_load_state(nphase_lbm_t h, const void* state_dev) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!state_dev) { h->err = "state buffer is NULL"; return NPHASE_EINVAL; }
+  size_t parts[5];
+  state_payload(h, parts);
+  StateHeader hdr;
+  HIPCHK(hipMemcpyAsync(&hdr, state_dev, sizeof(hdr), hipMemcpyDeviceToHost, h->stream), "load header");
+  HIPCHK(hipStreamSynchronize(h->stream), "load header sync");
+  if (hdr.magic != 0x4e5048415345) { h->err = "not a state buffer"; return NPHASE_EINVAL; }
+  const char* q = (const char*)state_dev + ALIGN;
+  void* dst[5] = {h->f[h->cur], h->g[h->cur], h->u[h->cur], h->pm[h->cur], h->mm};
+  for (int k = 0; k < 5; ++k) {
+    HIPCHK(hipMemcpyAsync(dst[k], q, parts[k], hipMemcpyDeviceToDevice, h->stream), "load copy");
+    q += parts[k];
+  }
+  h->t = hdr.t;
+  h->rho_bar = hdr.rho_bar;
+  refresh_args(h);
+  h->inited = true;
+  return NPHASE_OK;
+}
+
+const char* nphase_lbm_last_error(nphase_lbm_t h) {
+  if (!h) return "NULL handle";
+  return h->err.c_str();
+}
+
+const char* nphase_lbm_strerror(int status) {
+  switch (status) {
+    case NPHASE_OK: return "NPHASE_OK";
+    case NPHASE_EINVAL: return "NPHASE_EINVAL: invalid argument";
+    case NPHASE_ENOMEM: return "NPHASE_ENOMEM: buffer too small";
+    case NPHASE_EDEVICE: return "NPHASE_EDEVICE: HIP error";
+    case NPHASE_ENAN: return "NPHASE_ENAN: non-finite values";
+    case NPHASE_ESTATE: return "NPHASE_ESTATE: handle failed or not initialised";
+    case NPHASE_ENOTSUP: return "NPHASE_ENOTSUP: unsupported parameters";
+    default: return "unknown status";
+  }
+}
+
+int nphase_lbm_destroy(nphase_lbm_t h) {
+  delete h;
+  return NPHASE_OK;
+}
+
+}  // extern "C"

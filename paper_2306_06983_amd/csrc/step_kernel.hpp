@@ -1,0 +1,707 @@
+// Fused time step of the consistent and conservative N-phase LBM (one kernel per step).
+//
+// Per workgroup: one tile of TX x TY (x TZ) nodes, one node per thread (256 threads).
+//   stage 1  region = tile + 2-node halo: phi_p = sum_i f_{i,p} (Sec. 3 macroscopic
+//            recovery) for the evolved sets, phi_N = 1 - sum (Sec. 4 intro), and for
+//            Model B the pairwise fractions phi_pq = phi_p/(phi_p + phi_q) (Sec. 2.1);
+//            all into LDS.  Interior threads keep the first moments j_p of their node.
+//   stage 2  tile + 1-node halo: isotropic gradients (Sec. 3 closing paragraph), sources
+//            R_p of Model A / Model B (Sec. 2.1), mass-diffusion flux
+//            m_phi = -M sum_p rho_p (grad phi_p - R_p) (Sec. 2.2), and the antisymmetric
+//            tensor m_phi u^- - u^- m_phi with the lagged velocity, into LDS.
+//   stage 3  tile: correction force F_c = -div(m_phi u - u m_phi)/2 from that tensor,
+//            chemical potentials and the potential-form surface tension (Sec. 2.2),
+//            gravity, u, m, P (Sec. 3), the moment-space collisions of every evolved
+//            phase set and of the flow set in closed form (natural M, diagonal S:
+//            only the first-order rows relax with 1/tau_f for the phase field, only the
+//            second-order rows with the local 1/tau_g for the flow), push-streaming into
+//            the destination buffers, and the history fields u, phi, m_phi.
+//
+// Storage (SoA, x fastest, V nodes):
+//   f [NS][Q][V]   phase populations.  FP64: f_{i,p}.  FP32: deviations
+//                  f~_{i,p} = f_{i,p} - w_i phi_p^{t-1}(x) from the rest weights of the
+//                  previous-step local order parameter (which is stored anyway); the
+//                  exact rounding residual of phi^{t-1} + sum f~ in FP32 is added to the
+//                  rest deviation f~_0 the node writes, so the stored state keeps its mass.
+//   g [Q-1][V]     flow populations i = 1..Q-1 (g_0 feeds no moment used later: P takes
+//                  sum_{i != 0} g_i and c_0 = 0, so it is never stored).
+//   u [D][V]       velocity u^{t-1} (ping-pong: read at radius 1).
+//   pm [NS][V]     phi^{t-1} of the evolved sets (ping-pong: FP32 reads it at radius 2).
+//   mm [D][V]      m_phi^{t-1} (read and written at the own node only: in place).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lattice.hpp"
+
+namespace nphase {
+
+constexpr int MAXN = 8;
+constexpr int NTHREADS = 256;
+constexpr double NORMAL_EPS = 1e-12;   // |v|^2 > NORMAL_EPS^2 to normalise, else n = 0
+constexpr double PAIR_EPS = 1e-12;     // phi_p + phi_q > PAIR_EPS, else phi_pq = 1/2
+constexpr int MODE_STEP = 0;
+constexpr int MODE_FIELDS = 1;
+constexpr int MODEL_A = 0;
+constexpr int MODEL_B = 1;
+
+template <typename T>
+struct StepArgs {
+  const T* f_src;
+  T* f_dst;
+  const T* g_src;
+  T* g_dst;
+  const T* u_src;
+  T* u_dst;
+  const T* pm_src;
+  T* pm_dst;
+  T* mm;
+  double* phi_out;   // fields mode: [N][V]
+  double* u_out;     // fields mode: [D][V]
+  double* p_out;     // fields mode: [V]
+  int nx, ny, nz;
+  int ntx, nty, ntz, ntiles;
+  long long V;
+  int model_a_n;
+  T rho[MAXN];
+  T mu[MAXN];
+  T beta2[MAXN * MAXN];   // 2 beta_pq = 6 sigma_pq / eps
+  T kappa[MAXN * MAXN];   // k_pq = -3 eps sigma_pq / 4
+  T mob;                  // M
+  T s1;                   // 1 / tau_f
+  T four_over_eps;        // 4 / eps
+  T rho_bar;
+  T grav[3];
+};
+
+template <int LAT>
+struct TileShape;
+template <>
+struct TileShape<LAT_D2Q9> {
+  static constexpr int TX = 32, TY = 8, TZ = 1;
+};
+template <>
+struct TileShape<LAT_D3Q19> {
+  static constexpr int TX = 8, TY = 8, TZ = 4;
+};
+
+__device__ __forceinline__ int wrap(int v, int n) {
+  int r = v % n;
+  return r < 0 ? r + n : r;
+}
+
+// k-th node of the ring of width W around the box [W, E-W) of a region of extents
+// EX x EY (x EZ); 2D when EZ == 1.
+template <int W, int EX, int EY>
+__device__ __forceinline__ void ring2d(int j, int& rx, int& ry) {
+  if (j < W * EX) {
+    ry = j / EX;
+    rx = j % EX;
+  } else if (j < 2 * W * EX) {
+    const int jj = j - W * EX;
+    ry = EY - W + jj / EX;
+    rx = jj % EX;
+  } else {
+    const int jj = j - 2 * W * EX;
+    ry = W + jj / (2 * W);
+    const int c = jj % (2 * W);
+    rx = c < W ? c : EX - 2 * W + c;
+  }
+}
+
+template <int W, int EX, int EY, int EZ>
+__device__ __forceinline__ void ring_coord(int k, int& rx, int& ry, int& rz) {
+  if constexpr (EZ == 1) {
+    rz = 0;
+    ring2d<W, EX, EY>(k, rx, ry);
+  } else {
+    constexpr int FULL = 2 * W * EX * EY;
+    constexpr int P2 = 2 * W * EX + 2 * W * (EY - 2 * W);
+    if (k < FULL) {
+      const int p = k / (EX * EY);
+      rz = p < W ? p : EZ - 2 * W + p;
+      const int j = k % (EX * EY);
+      ry = j / EX;
+      rx = j % EX;
+    } else {
+      const int kk = k - FULL;
+      rz = W + kk / P2;
+      ring2d<W, EX, EY>(kk % P2, rx, ry);
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T gprime(T p) {  // g(phi) = phi^2 (1 - phi)^2
+  return T(2) * p * (T(1) - p) * (T(1) - T(2) * p);
+}
+
+// Model B pairwise fraction phi_pq = phi_p / (phi_p + phi_q), 1/2 where both vanish
+template <typename T>
+__device__ __forceinline__ T pair_fraction(T pp, T pq) {
+  const T s = pp + pq;
+  return (s > T(PAIR_EPS)) ? pp / s : T(0.5);
+}
+
+template <typename T, int LAT, int N, bool SA, int MODEL, int MODE>
+__global__ void __launch_bounds__(NTHREADS) nphase_step_kernel(const StepArgs<T> a) {
+  using L = Lattice<LAT>;
+  constexpr int D = L::D;
+  constexpr int Q = L::Q;
+  constexpr int NS = SA ? N : N - 1;
+  constexpr int NP = N * (N - 1) / 2;
+  constexpr bool DEV = sizeof(T) == 4;   // FP32 deviation storage
+  using TS = TileShape<LAT>;
+  constexpr int TX = TS::TX, TY = TS::TY, TZ = (D == 3) ? TS::TZ : 1;
+  static_assert(TX * TY * TZ == NTHREADS, "one node per thread");
+  constexpr int RX = TX + 4, RY = TY + 4, RZ = (D == 3) ? TZ + 4 : 1;
+  constexpr int NR = RX * RY * RZ;
+  constexpr int IX = TX + 2, IY = TY + 2, IZ = (D == 3) ? TZ + 2 : 1;
+  constexpr int NI = IX * IY * IZ;
+  constexpr int HZ = (D == 3) ? 2 : 0;   // halo offset in z of the region
+  constexpr int NW = (D == 3) ? 3 : 1;   // independent components of the antisymmetric tensor
+  constexpr T CS2 = T(1) / T(3);
+
+  // Model B pair fractions are staged in LDS when they fit a 64 KiB budget, otherwise
+  // they are recomputed from phi at every stencil point.
+  constexpr bool PF_LDS =
+      (MODEL == MODEL_B) && (sizeof(T) * ((NS + NP) * NR + NW * NI) <= 65536);
+  __shared__ T s_phi[NS][NR];
+  __shared__ T s_pf[PF_LDS ? NP : 1][PF_LDS ? NR : 1];
+  __shared__ T s_w[NW][NI];
+
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const long long V = a.V;
+  const int t = threadIdx.x;
+
+  // XCD-aware tile order: consecutive workgroup ids go round-robin over the 8 XCDs, so
+  // give each XCD a contiguous range of tiles (raster order) to share halos in its L2.
+  int tile;
+  {
+    const int b = blockIdx.x;
+    const int nt = a.ntiles;
+    const int q = nt / 8, r8 = nt % 8;
+    const int xcd = b % 8, loc = b / 8;
+    tile = xcd * q + (xcd < r8 ? xcd : r8) + loc;
+  }
+  const int tx0 = (tile % a.ntx) * TX;
+  const int ty0 = ((tile / a.ntx) % a.nty) * TY;
+  const int tz0 = (tile / (a.ntx * a.nty)) * TZ;
+
+  auto region_gidx = [&](int rx, int ry, int rz) -> long long {
+    const int gx = wrap(tx0 - 2 + rx, nx);
+    const int gy = wrap(ty0 - 2 + ry, ny);
+    const int gz = (D == 3) ? wrap(tz0 - 2 + rz, nz) : 0;
+    return (long long)gx + (long long)nx * ((long long)gy + (long long)ny * gz);
+  };
+
+  // own node
+  const int lx = t % TX, ly = (t / TX) % TY, lz = t / (TX * TY);
+  const int ox = tx0 + lx, oy = ty0 + ly, oz = tz0 + lz;
+  const bool valid = (ox < nx) && (oy < ny) && (D == 2 || oz < nz);
+  const int r_own = (lx + 2) + RX * ((ly + 2) + RY * (lz + HZ));
+  const int i_own = (lx + 1) + IX * ((ly + 1) + IY * (lz + (D == 3 ? 1 : 0)));
+  const long long g_own = region_gidx(lx + 2, ly + 2, lz + HZ);
+
+  // region offsets of the lattice directions
+  auto roff = [&](int i) constexpr { return L::c(i, 0) + RX * (L::c(i, 1) + RY * L::c(i, 2)); };
+  auto ioff = [&](int i) constexpr { return L::c(i, 0) + IX * (L::c(i, 1) + IY * L::c(i, 2)); };
+
+  // ---------------------------------------------------------------- stage 1
+  T j_own[NS][D];
+  T pm_own[NS];
+  T res_own[NS];   // FP32: exact rounding residual of phi = phi^{t-1} + sum f~ (own node)
+  auto stage1 = [&](int r, long long gi, bool own) {
+    T ph[N];
+#pragma unroll
+    for (int p = 0; p < NS; ++p) {
+      T v[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) v[i] = a.f_src[(long long)(p * Q + i) * V + gi];
+      T s = v[0];
+#pragma unroll
+      for (int i = 1; i < Q; ++i) s += v[i];
+      if constexpr (DEV) {
+        const T pm = a.pm_src[(long long)p * V + gi];
+        const T sum = pm + s;
+        if (own) {
+          // two-sum: (pm + s) - sum exactly; it is re-injected into the rest deviation
+          // written by this node so that the stored state keeps the mass it had
+          const T bb = sum - pm;
+          res_own[p] = (pm - (sum - bb)) + (s - bb);
+          pm_own[p] = pm;
+        }
+        s = sum;
+      }
+      ph[p] = s;
+      s_phi[p][r] = s;
+      if (own) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          T jj = T(0);
+#pragma unroll
+          for (int i = 1; i < Q; ++i) {
+            if (L::c(i, d) == 1) jj += v[i];
+            if (L::c(i, d) == -1) jj -= v[i];
+          }
+          j_own[p][d] = jj;
+        }
+      }
+    }
+    if constexpr (!SA) {
+      T rest = ph[0];
+#pragma unroll
+      for (int p = 1; p < NS; ++p) rest += ph[p];
+      ph[N - 1] = T(1) - rest;
+    }
+    if constexpr (PF_LDS) {
+      int k = 0;
+#pragma unroll
+      for (int p = 0; p < N; ++p) {
+#pragma unroll
+        for (int q = p + 1; q < N; ++q) {
+          s_pf[k][r] = pair_fraction(ph[p], ph[q]);
+          ++k;
+        }
+      }
+    }
+  };
+  stage1(r_own, g_own, true);
+  {
+    constexpr int NRING = NR - NTHREADS;
+    for (int k = t; k < NRING; k += NTHREADS) {
+      int rx, ry, rz;
+      ring_coord<2, RX, RY, RZ>(k, rx, ry, rz);
+      stage1(rx + RX * (ry + RY * rz), region_gidx(rx, ry, rz), false);
+    }
+  }
+  __syncthreads();
+
+  // ---------------------------------------------------------------- stage 2
+  // phi of all N phases at region node r
+  auto phi_at = [&](int r, T* ph) {
+#pragma unroll
+    for (int p = 0; p < NS; ++p) ph[p] = s_phi[p][r];
+    if constexpr (!SA) {
+      T rest = ph[0];
+#pragma unroll
+      for (int p = 1; p < NS; ++p) rest += ph[p];
+      ph[N - 1] = T(1) - rest;
+    }
+  };
+  auto normalize = [&](T* v) {
+    T n2 = v[0] * v[0];
+#pragma unroll
+    for (int d = 1; d < D; ++d) n2 += v[d] * v[d];
+    if (n2 > T(NORMAL_EPS * NORMAL_EPS)) {
+      const T inv = T(1) / sqrt(n2);
+#pragma unroll
+      for (int d = 0; d < D; ++d) v[d] *= inv;
+    } else {
+#pragma unroll
+      for (int d = 0; d < D; ++d) v[d] = T(0);
+    }
+  };
+
+  T G[N][D], Lp[N], R[N][D], phc[N], mphi[D];
+  // computes G, R (and L when lap) at region node r, then m_phi
+  auto stage2 = [&](int r, bool lap) {
+    T H[(MODEL == MODEL_B) ? NP : 1][D];   // Model B: gradients of the pair fractions
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+      Lp[p] = T(0);
+#pragma unroll
+      for (int d = 0; d < D; ++d) G[p][d] = T(0);
+    }
+    if constexpr (MODEL == MODEL_B) {
+#pragma unroll
+      for (int k = 0; k < NP; ++k)
+#pragma unroll
+        for (int d = 0; d < D; ++d) H[k][d] = T(0);
+    }
+    phi_at(r, phc);
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      T ph[N];
+      phi_at(r + roff(i), ph);
+      const T wg = T(3) * T(L::w(i));
+      const T wl = T(6) * T(L::w(i));
+#pragma unroll
+      for (int p = 0; p < N; ++p) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          if (L::c(i, d) == 1) G[p][d] += wg * ph[p];
+          if (L::c(i, d) == -1) G[p][d] -= wg * ph[p];
+        }
+        if (lap) Lp[p] += wl * (ph[p] - phc[p]);
+      }
+      if constexpr (MODEL == MODEL_B) {
+        int k = 0;
+#pragma unroll
+        for (int p = 0; p < N; ++p) {
+#pragma unroll
+          for (int q = p + 1; q < N; ++q) {
+            T v;
+            if constexpr (PF_LDS) v = s_pf[k][r + roff(i)];
+            else v = pair_fraction(ph[p], ph[q]);
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+              if (L::c(i, d) == 1) H[k][d] += wg * v;
+              if (L::c(i, d) == -1) H[k][d] -= wg * v;
+            }
+            ++k;
+          }
+        }
+      }
+    }
+    if constexpr (MODEL == MODEL_A) {
+      T an[D], pw[N], nv[N][D], ap[N];
+      T spw = T(0);
+#pragma unroll
+      for (int d = 0; d < D; ++d) an[d] = T(0);
+#pragma unroll
+      for (int p = 0; p < N; ++p) {
+        ap[p] = a.four_over_eps * phc[p] * (T(1) - phc[p]);
+#pragma unroll
+        for (int d = 0; d < D; ++d) nv[p][d] = G[p][d];
+        normalize(nv[p]);
+        T x = phc[p];
+        for (int k = 1; k < a.model_a_n; ++k) x *= phc[p];
+        pw[p] = x;
+        spw = (p == 0) ? x : spw + x;
+#pragma unroll
+        for (int d = 0; d < D; ++d) an[d] = (p == 0) ? ap[p] * nv[p][d] : an[d] + ap[p] * nv[p][d];
+      }
+#pragma unroll
+      for (int p = 0; p < N; ++p) {
+        const T lam = pw[p] / spw;
+#pragma unroll
+        for (int d = 0; d < D; ++d) R[p][d] = ap[p] * nv[p][d] - lam * an[d];
+      }
+    } else {
+#pragma unroll
+      for (int p = 0; p < N; ++p)
+#pragma unroll
+        for (int d = 0; d < D; ++d) R[p][d] = T(0);
+      int k = 0;
+#pragma unroll
+      for (int p = 0; p < N; ++p) {
+#pragma unroll
+        for (int q = p + 1; q < N; ++q) {
+          normalize(H[k]);
+          const T coef = a.four_over_eps * phc[p] * phc[q];
+#pragma unroll
+          for (int d = 0; d < D; ++d) {
+            R[p][d] += coef * H[k][d];
+            R[q][d] += coef * (-H[k][d]);
+          }
+          ++k;
+        }
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      T acc = a.rho[0] * (G[0][d] - R[0][d]);
+#pragma unroll
+      for (int p = 1; p < N; ++p) acc += a.rho[p] * (G[p][d] - R[p][d]);
+      mphi[d] = -a.mob * acc;
+    }
+  };
+  // antisymmetric tensor A_ab = m_a u^-_b - u^-_a m_b: components (xy) or (xy, xz, yz)
+  auto store_w = [&](int iq, long long gi) {
+    T um[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) um[d] = a.u_src[(long long)d * V + gi];
+    s_w[0][iq] = mphi[0] * um[1] - um[0] * mphi[1];
+    if constexpr (D == 3) {
+      s_w[1][iq] = mphi[0] * um[2] - um[0] * mphi[2];
+      s_w[2][iq] = mphi[1] * um[2] - um[1] * mphi[2];
+    }
+  };
+  {
+    constexpr int NIRING = NI - NTHREADS;
+    for (int k = t; k < NIRING; k += NTHREADS) {
+      int ix, iy, iz;
+      ring_coord<1, IX, IY, IZ>(k, ix, iy, iz);
+      const int rz = (D == 3) ? iz + 1 : 0;
+      const int r = (ix + 1) + RX * ((iy + 1) + RY * rz);
+      stage2(r, false);
+      store_w(ix + IX * (iy + IY * iz), region_gidx(ix + 1, iy + 1, rz));
+    }
+  }
+  // own node last so that G, L, R, m_phi stay in registers for stage 3
+  stage2(r_own, true);
+  store_w(i_own, g_own);
+  __syncthreads();
+
+  if (!valid) return;
+
+  // ---------------------------------------------------------------- stage 3
+  const T* phi_own = phc;   // phi of all N phases at the own node
+  // correction force F_c,b = -1/2 sum_a D_a A_ab
+  T Fc[D];
+  {
+    T DW[NW][D];
+#pragma unroll
+    for (int k = 0; k < NW; ++k)
+#pragma unroll
+      for (int d = 0; d < D; ++d) DW[k][d] = T(0);
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const T wg = T(3) * T(L::w(i));
+#pragma unroll
+      for (int k = 0; k < NW; ++k) {
+        const T v = s_w[k][i_own + ioff(i)];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          if (L::c(i, d) == 1) DW[k][d] += wg * v;
+          if (L::c(i, d) == -1) DW[k][d] -= wg * v;
+        }
+      }
+    }
+    if constexpr (D == 2) {
+      Fc[0] = T(0.5) * DW[0][1];
+      Fc[1] = T(-0.5) * DW[0][0];
+    } else {
+      Fc[0] = T(0.5) * (DW[0][1] + DW[1][2]);
+      Fc[1] = T(-0.5) * DW[0][0] + T(0.5) * DW[2][2];
+      Fc[2] = T(-0.5) * (DW[1][0] + DW[2][1]);
+    }
+  }
+
+  // mixing, local relaxation
+  T rho = a.rho[0] * phi_own[0], mu = a.mu[0] * phi_own[0];
+#pragma unroll
+  for (int p = 1; p < N; ++p) {
+    rho += a.rho[p] * phi_own[p];
+    mu += a.mu[p] * phi_own[p];
+  }
+  const T tau_g = T(0.5) + mu / (rho * CS2);
+  const T s2 = T(1) / tau_g;
+
+  // chemical potentials and the surface tension
+  T F[D], grho[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    F[d] = T(0);
+    grho[d] = a.rho[0] * G[0][d];
+  }
+#pragma unroll
+  for (int p = 1; p < N; ++p)
+#pragma unroll
+    for (int d = 0; d < D; ++d) grho[d] += a.rho[p] * G[p][d];
+  {
+    T gp[N];
+#pragma unroll
+    for (int p = 0; p < N; ++p) gp[p] = gprime(phi_own[p]);
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+      T m = T(0);
+#pragma unroll
+      for (int q = 0; q < N; ++q)
+        if (q != p) m += a.beta2[p * MAXN + q] * (gp[p] - gprime(phi_own[p] + phi_own[q]));
+#pragma unroll
+      for (int q = 0; q < N; ++q)
+        if (q != p) m -= a.kappa[p * MAXN + q] * Lp[q];
+#pragma unroll
+      for (int d = 0; d < D; ++d) F[d] += m * G[p][d];
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < D; ++d) F[d] = F[d] + (rho - a.rho_bar) * a.grav[d] + Fc[d];
+
+  // flow moments
+  T gv[Q];
+  gv[0] = T(0);
+#pragma unroll
+  for (int i = 1; i < Q; ++i) gv[i] = a.g_src[(long long)(i - 1) * V + g_own];
+  T jg[D], Pi[D][D], sumg = T(0);
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    jg[d] = T(0);
+#pragma unroll
+    for (int e = 0; e < D; ++e) Pi[d][e] = T(0);
+  }
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    sumg += gv[i];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      if (L::c(i, d) == 1) jg[d] += gv[i];
+      if (L::c(i, d) == -1) jg[d] -= gv[i];
+#pragma unroll
+      for (int e = 0; e < D; ++e)
+        if (L::c(i, d) * L::c(i, e) == 1) Pi[d][e] += gv[i];
+        else if (L::c(i, d) * L::c(i, e) == -1) Pi[d][e] -= gv[i];
+    }
+  }
+  T u[D], m[D], um[D], mm_prev[D];
+  const T inv_rho = T(1) / rho;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    u[d] = (jg[d] + T(0.5) * F[d]) * inv_rho;
+    m[d] = rho * u[d] + mphi[d];
+    um[d] = a.u_src[(long long)d * V + g_own];
+    mm_prev[d] = a.mm[(long long)d * V + g_own];
+  }
+  T phm[N];
+#pragma unroll
+  for (int p = 0; p < NS; ++p) {
+    if constexpr (DEV) phm[p] = pm_own[p];
+    else phm[p] = a.pm_src[(long long)p * V + g_own];
+  }
+  if constexpr (!SA) {
+    T rest = phm[0];
+#pragma unroll
+    for (int p = 1; p < NS; ++p) rest += phm[p];
+    phm[N - 1] = T(1) - rest;
+  }
+  T rho_prev = a.rho[0] * phm[0];
+#pragma unroll
+  for (int p = 1; p < N; ++p) rho_prev += a.rho[p] * phm[p];
+  T mu_dot = m[0] * u[0], mu_prev = (rho_prev * um[0] + mm_prev[0]) * um[0], ugr = u[0] * grho[0];
+#pragma unroll
+  for (int d = 1; d < D; ++d) {
+    mu_dot += m[d] * u[d];
+    mu_prev += (rho_prev * um[d] + mm_prev[d]) * um[d];
+    ugr += u[d] * grho[d];
+  }
+  constexpr T w0 = T(L::w(0));
+  const T P = CS2 / (T(1) - w0) *
+              (sumg + T(0.5) * ugr - w0 * mu_dot / (T(2) * CS2) +
+               w0 * T(0.5) * (mu_dot - mu_prev) / (T(2) * CS2));
+
+  if constexpr (MODE == MODE_FIELDS) {
+    if (a.phi_out) {
+#pragma unroll
+      for (int p = 0; p < N; ++p) a.phi_out[(long long)p * V + g_own] = (double)phi_own[p];
+    }
+    if (a.u_out) {
+#pragma unroll
+      for (int d = 0; d < D; ++d) a.u_out[(long long)d * V + g_own] = (double)u[d];
+    }
+    if (a.p_out) a.p_out[g_own] = (double)P;
+    return;
+  } else {
+    // destination node indices of the push-streaming
+    int X[3], Y[3], Z[3];
+    X[0] = wrap(ox - 1, nx); X[1] = ox; X[2] = wrap(ox + 1, nx);
+    Y[0] = wrap(oy - 1, ny); Y[1] = oy; Y[2] = wrap(oy + 1, ny);
+    if constexpr (D == 3) {
+      Z[0] = wrap(oz - 1, nz); Z[1] = oz; Z[2] = wrap(oz + 1, nz);
+    } else {
+      Z[0] = Z[1] = Z[2] = 0;
+    }
+    auto dest = [&](int i) -> long long {
+      return (long long)X[L::c(i, 0) + 1] +
+             (long long)nx * ((long long)Y[L::c(i, 1) + 1] + (long long)ny * Z[L::c(i, 2) + 1]);
+    };
+
+    // ---- phase-field collision (closed form of f - M^-1 S M (f - f^eq) + (I - M^-1 S M/2) R)
+    //   f*_i = w_i [phi + c_i.(3 phi u + Z/2)] + [axis i] c_i.D / 2,
+    //   Z = 3 d_t(phi u) + R_p,  D = (1 - s1)(j - phi u + c_s^2 Z / 2)
+#pragma unroll
+    for (int p = 0; p < NS; ++p) {
+      const T ph = phi_own[p];
+      T Zp[D], A[D], Dp[D];
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        Zp[d] = T(3) * (ph * u[d] - phm[p] * um[d]) + R[p][d];
+        A[d] = T(3) * ph * u[d] + T(0.5) * Zp[d];
+        Dp[d] = (T(1) - a.s1) * (j_own[p][d] - ph * u[d] + T(0.5) * CS2 * Zp[d]);
+      }
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        T cA = T(0), cD = T(0);
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          if (L::c(i, d) == 1) { cA += A[d]; cD += Dp[d]; }
+          if (L::c(i, d) == -1) { cA -= A[d]; cD -= Dp[d]; }
+        }
+        const T wi = T(L::w(i));
+        T fs;
+        if constexpr (DEV) {
+          // deviation from the rest weights of the destination's phi (= its next phi^{t-1})
+          if (i == 0) {
+            fs = wi * cA + res_own[p];
+          } else {
+            const T dphi = ph - s_phi[p][r_own + roff(i)];
+            fs = wi * (dphi + cA);
+          }
+        } else {
+          fs = wi * (ph + cA);
+        }
+        if (cnorm2<L>(i) == 1) fs += T(0.5) * cD;
+        a.f_dst[(long long)(p * Q + i) * V + dest(i)] = fs;
+      }
+      a.pm_dst[(long long)p * V + g_own] = ph;
+    }
+
+    // ---- flow collision: g* = g^eq + F_i/2 + (1 - s2) M^-1 [second-order rows of
+    //      (m - m^eq + MF/2)]; M^-1 columns: c_a^2 -> +1/2 on +-e_a (and -1 at rest, not
+    //      stored), c_a c_b -> c_a c_b / 4 on the (a,b) diagonals.
+    T T2[D][D];
+    T trT = T(0);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+#pragma unroll
+      for (int e = 0; e < D; ++e) {
+        T2[d][e] = u[d] * F[e] + F[d] * u[e] +
+                   T(0.5) * ((mphi[d] * u[e] + u[d] * mphi[e]) -
+                             (mm_prev[d] * um[e] + um[d] * mm_prev[e])) +
+                   CS2 * (u[d] * grho[e] + grho[d] * u[e]);
+      }
+      trT += T2[d][d];
+    }
+    T Nn[D][D];   // Pi - Pi^eq + M_2F / 2 (second-order non-equilibrium + source)
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+#pragma unroll
+      for (int e = 0; e < D; ++e) {
+        const T eq = ((d == e) ? P : T(0)) + T(0.5) * (m[d] * u[e] + m[e] * u[d]);
+        const T m2f = T2[d][e] + ((d == e) ? CS2 * ugr : T(0));
+        Nn[d][e] = Pi[d][e] - eq + T(0.5) * m2f;
+      }
+    const T oms2 = T(1) - s2;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      T cu = T(0), cm = T(0), cF = T(0), cTc = T(0);
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const int cd = L::c(i, d);
+        if (cd != 0) {
+          cu += T(cd) * u[d];
+          cm += T(cd) * m[d];
+          cF += T(cd) * F[d];
+#pragma unroll
+          for (int e = 0; e < D; ++e)
+            if (L::c(i, e) != 0) cTc += T(cd * L::c(i, e)) * T2[d][e];
+        }
+      }
+      const T wi = T(L::w(i));
+      const T geq = wi * (T(3) * P + T(3) * rho * cu + T(4.5) * cm * cu - T(1.5) * mu_dot);
+      const T Fi = wi * (ugr + T(3) * cF + T(4.5) * (cTc - CS2 * trT));
+      T corr = T(0);
+      if (cnorm2<L>(i) == 1) {
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+          if (L::c(i, d) != 0) corr = T(0.5) * Nn[d][d];
+      } else {
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+#pragma unroll
+          for (int e = d + 1; e < D; ++e)
+            if (L::c(i, d) != 0 && L::c(i, e) != 0)
+              corr = T(0.25) * T(L::c(i, d) * L::c(i, e)) * Nn[d][e];
+      }
+      a.g_dst[(long long)(i - 1) * V + dest(i)] = geq + T(0.5) * Fi + oms2 * corr;
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      a.u_dst[(long long)d * V + g_own] = u[d];
+      a.mm[(long long)d * V + g_own] = mphi[d];
+    }
+  }
+}
+
+}  // namespace nphase
