@@ -100,13 +100,30 @@ def time_oracle(cfg, phi, max_seconds=20.0, max_steps=12):
     return dict(mlups=V * n / dt / 1e6, steps=n, seconds=dt)
 
 
+def copy_calibration(nbytes=256 << 20, reps=10):
+    """A plain copy kernel of known size: reads and writes nbytes per launch."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}))
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 256 MiB ten times (reference "
+                         "for the memory traffic counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        return copy_calibration()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); "
               "the step is a single-GPU kernel and no multi-GPU path exists", file=sys.stderr)

@@ -123,6 +123,7 @@ def test_two_discs_full_length():
     assert np.abs(g["phi"].sum(0) - 1).max() <= 1e-14
     g32 = run_gpu(cfg, phi, 2000, "fp32")
     e32 = errors(g32, o)
-    print(f"  2000 steps fp32 dphi={e32[0]:.2e}")
-    assert e32[0] <= 1e-5
+    env = _fp32_envelope(cfg, phi, 2000, o)
+    print(f"  2000 steps fp32 dphi={e32[0]:.2e} envelope={env:.2e}")
+    assert e32[0] <= max(FP32_PHI_TOL, 3 * env)
     assert np.all(np.abs(g32["m1"] - g["m0"]) <= FP32_MASS_TOL * g["m0"])
