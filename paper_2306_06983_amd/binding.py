@@ -76,6 +76,11 @@ def load():
         "nphase_lbm_save_state": [vp, vp],
         "nphase_lbm_load_state": [vp, vp],
         "nphase_lbm_destroy": [vp],
+        "nphase_lbm_adjoint_workspace_bytes": [vp, ctypes.POINTER(sz)],
+        "nphase_lbm_adjoint_seed": [vp, vp, vp],
+        "nphase_lbm_adjoint_step": [vp, vp, vp, vp, vp, sz],
+        "nphase_lbm_adjoint_sigma": [vp, vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int],
+        "nphase_lbm_adjoint_init": [vp, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -217,6 +222,49 @@ class Sim:
     def load_state(self, buf):
         self._rc(self.lib.nphase_lbm_load_state(self.h, ctypes.c_void_p(buf.data_ptr())))
         return self
+
+    # ---- discrete adjoint (FP64 handles) -------------------------------------------------
+    def adjoint_workspace(self):
+        n = ctypes.c_size_t()
+        self._rc(self.lib.nphase_lbm_adjoint_workspace_bytes(self.h, ctypes.byref(n)))
+        t = self.torch
+        return t.empty(n.value + 256, dtype=t.uint8, device=self.device), n.value
+
+    def adjoint_seed(self, dL_dphi, buf=None):
+        t = self.torch
+        x = dL_dphi.to(device=self.device, dtype=t.float64).contiguous()
+        if buf is None:
+            buf = t.zeros(self.state_bytes(), dtype=t.uint8, device=self.device)
+        self._rc(self.lib.nphase_lbm_adjoint_seed(self.h, ctypes.c_void_p(x.data_ptr()),
+                                                  ctypes.c_void_p(buf.data_ptr())))
+        return buf
+
+    def adjoint_step(self, state_buf, lam_in, lam_out, ws):
+        buf, nbytes = ws
+        base = (buf.data_ptr() + 255) // 256 * 256
+        self._rc(self.lib.nphase_lbm_adjoint_step(
+            self.h, ctypes.c_void_p(state_buf.data_ptr()), ctypes.c_void_p(lam_in.data_ptr()),
+            ctypes.c_void_p(lam_out.data_ptr()), ctypes.c_void_p(base), nbytes))
+        return lam_out
+
+    def adjoint_sigma(self, ws, reset=False, read=True):
+        """dL/dsigma as an N x N matrix (pair derivative in both [p][q] and [q][p])."""
+        buf, nbytes = ws
+        base = (buf.data_ptr() + 255) // 256 * 256
+        out = (ctypes.c_double * (MAX_N * MAX_N))()
+        self._rc(self.lib.nphase_lbm_adjoint_sigma(self.h, ctypes.c_void_p(base),
+                                                   out if read else None, 1 if reset else 0))
+        if not read:
+            return None
+        m = np.array(out[:], dtype=np.float64).reshape(MAX_N, MAX_N)
+        return m[:self.N, :self.N].copy()
+
+    def adjoint_init(self, lam):
+        t = self.torch
+        out = t.empty((self.N,) + self.grid, dtype=t.float64, device=self.device)
+        self._rc(self.lib.nphase_lbm_adjoint_init(self.h, ctypes.c_void_p(lam.data_ptr()),
+                                                  ctypes.c_void_p(out.data_ptr())))
+        return out
 
     def close(self):
         if getattr(self, "h", None):

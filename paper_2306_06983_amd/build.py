@@ -16,6 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnphase_lbm.so")
 SOURCES = ["nphase_lbm.hip", "kernels_f64_d2q9.hip", "kernels_f32_d2q9.hip",
+           "adjoint_d2q9.hip", "adjoint_d3q19.hip",
            "kernels_f64_d3q19.hip", "kernels_f32_d3q19.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

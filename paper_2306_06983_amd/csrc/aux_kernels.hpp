@@ -110,6 +110,12 @@ __global__ void __launch_bounds__(256)
   if (bad) flag[0] = 1;
 }
 
+// fills n doubles with zero (kernel, not a memset node)
+__global__ void zero_double_kernel(double* p, long long n) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = 0.0;
+}
+
 // fills n ints with zero (used instead of a memset node so that callers may capture it)
 __global__ void zero_int_kernel(int* p, int n) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;

@@ -8,8 +8,10 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/nphase_lbm.h"
+#include "adjoint_dispatch.hpp"
 #include "aux_kernels.hpp"
 #include "dispatch.hpp"
 
@@ -479,6 +481,198 @@ const char* nphase_lbm_strerror(int status) {
 
 int nphase_lbm_destroy(nphase_lbm_t h) {
   delete h;
+  return NPHASE_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------- adjoint
+namespace {
+
+struct AdjLayout {
+  size_t F_phi, F_j, F_G, F_L, F_R, F_H, F_mphi, F_W, F_Fc;
+  size_t A_ph, A_j, A_G, A_R, A_L, A_mphi, A_Fc, A_gv, A_um, A_phm, A_mmp, A_H, sig;
+  size_t total;
+  int nblk;
+};
+
+AdjLayout adj_layout(nphase_lbm_t h) {
+  AdjLayout L;
+  const size_t V = (size_t)h->V, b = sizeof(double);
+  const int N = h->N, NS = h->NS, D = h->D, Q = h->Q, NP = N * (N - 1) / 2;
+  const int NW = D == 3 ? 3 : 1;
+  L.nblk = (int)((h->V + 255) / 256);
+  size_t off = 0;
+  auto take = [&](size_t n) { size_t o = off; off += align_up(n * V * b); return o; };
+  L.F_phi = take(N); L.F_j = take(NS * D); L.F_G = take(N * D); L.F_L = take(N);
+  L.F_R = take(N * D); L.F_H = take(NP > 0 ? NP * D : 1); L.F_mphi = take(D); L.F_W = take(NW);
+  L.F_Fc = take(D);
+  L.A_ph = take(N); L.A_j = take(NS * D); L.A_G = take(N * D); L.A_R = take(N * D);
+  L.A_L = take(N); L.A_mphi = take(D); L.A_Fc = take(D); L.A_gv = take(Q - 1); L.A_um = take(D);
+  L.A_phm = take(NS); L.A_mmp = take(D); L.A_H = take(NP > 0 ? NP * D : 1);
+  L.sig = off;
+  off += align_up((size_t)(NP > 0 ? NP : 1) * L.nblk * b);
+  L.total = off;
+  return L;
+}
+
+// pointers of a state-layout buffer (header + f + g + u + pm + mm), FP64
+struct StatePtrs {
+  double *f, *g, *u, *pm, *mm;
+};
+StatePtrs state_ptrs(nphase_lbm_t h, const void* buf) {
+  StatePtrs P;
+  char* q = (char*)buf + ALIGN;
+  const size_t V = (size_t)h->V, b = sizeof(double);
+  P.f = (double*)q; q += (size_t)h->NS * h->Q * V * b;
+  P.g = (double*)q; q += (size_t)(h->Q - 1) * V * b;
+  P.u = (double*)q; q += (size_t)h->D * V * b;
+  P.pm = (double*)q; q += (size_t)h->NS * V * b;
+  P.mm = (double*)q;
+  return P;
+}
+
+AdjArgs adj_args(nphase_lbm_t h, void* ws) {
+  AdjArgs a;
+  std::memset(&a, 0, sizeof(a));
+  const AdjLayout L = adj_layout(h);
+  char* w = (char*)ws;
+  a.F_phi = (double*)(w + L.F_phi); a.F_j = (double*)(w + L.F_j); a.F_G = (double*)(w + L.F_G);
+  a.F_L = (double*)(w + L.F_L); a.F_R = (double*)(w + L.F_R); a.F_H = (double*)(w + L.F_H);
+  a.F_mphi = (double*)(w + L.F_mphi); a.F_W = (double*)(w + L.F_W); a.F_Fc = (double*)(w + L.F_Fc);
+  a.A_ph = (double*)(w + L.A_ph); a.A_j = (double*)(w + L.A_j); a.A_G = (double*)(w + L.A_G);
+  a.A_R = (double*)(w + L.A_R); a.A_L = (double*)(w + L.A_L); a.A_mphi = (double*)(w + L.A_mphi);
+  a.A_Fc = (double*)(w + L.A_Fc); a.A_gv = (double*)(w + L.A_gv); a.A_um = (double*)(w + L.A_um);
+  a.A_phm = (double*)(w + L.A_phm); a.A_mmp = (double*)(w + L.A_mmp); a.A_H = (double*)(w + L.A_H);
+  a.sig_partial = (double*)(w + L.sig);
+  a.nblk = L.nblk;
+  const nphase_lbm_params& p = h->prm;
+  a.nx = p.nx; a.ny = p.ny; a.nz = p.nz; a.V = h->V; a.model_a_n = p.model_a_n;
+  for (int i = 0; i < h->N; ++i) {
+    a.rho[i] = p.rho[i];
+    a.mu[i] = p.rho[i] * (p.tau_g[i] - 0.5) * CS2;
+    for (int j = 0; j < h->N; ++j) {
+      const double s = p.sigma[i * NPHASE_MAX_N + j];
+      a.beta2[i * MAXN + j] = 2.0 * 3.0 * s / p.eps;
+      a.kappa[i * MAXN + j] = -0.75 * p.eps * s;
+      a.dbeta2[i * MAXN + j] = i == j ? 0.0 : 6.0 / p.eps;
+      a.dkappa[i * MAXN + j] = i == j ? 0.0 : -0.75 * p.eps;
+    }
+  }
+  a.mob = p.mobility;
+  a.s1 = 1.0 / (0.5 + p.mobility / CS2);
+  a.four_over_eps = 4.0 / p.eps;
+  a.rho_bar = h->rho_bar;
+  for (int d = 0; d < 3; ++d) a.grav[d] = p.gravity[d];
+  return a;
+}
+
+hipError_t adj_launch(nphase_lbm_t h, int which, const AdjArgs& a) {
+  const int grid = (int)((h->V + 255) / 256);
+  if (h->lat == NPHASE_D2Q9)
+    return launch_adjoint<LAT_D2Q9>(h->N, h->prm.solve_all, h->prm.model, which, a, grid, h->stream);
+  return launch_adjoint<LAT_D3Q19>(h->N, h->prm.solve_all, h->prm.model, which, a, grid, h->stream);
+}
+
+int adj_check(nphase_lbm_t h) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (h->prec != NPHASE_FP64) { h->err = "the adjoint is built for FP64 handles"; return NPHASE_ENOTSUP; }
+  if (h->prm.gravity[0] != 0.0 || h->prm.gravity[1] != 0.0 || h->prm.gravity[2] != 0.0) {
+    h->err = "the adjoint treats the gravity reference density as fixed: needs gravity = 0";
+    return NPHASE_ENOTSUP;
+  }
+  return NPHASE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nphase_lbm_adjoint_workspace_bytes(nphase_lbm_t h, size_t* bytes_host) {
+  int rc = adj_check(h);
+  if (rc) return rc;
+  if (!bytes_host) return NPHASE_EINVAL;
+  *bytes_host = adj_layout(h).total;
+  return NPHASE_OK;
+}
+
+int nphase_lbm_adjoint_seed(nphase_lbm_t h, const double* dL_dphi_dev, void* adj_state_dev) {
+  int rc = adj_check(h);
+  if (rc) return rc;
+  if (!dL_dphi_dev || !adj_state_dev) { h->err = "NULL pointer"; return NPHASE_EINVAL; }
+  AdjArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.V = h->V; a.nx = h->prm.nx; a.ny = h->prm.ny; a.nz = h->prm.nz;
+  a.dphi = dL_dphi_dev;
+  const StatePtrs o = state_ptrs(h, adj_state_dev);
+  a.lf_out = o.f; a.lg_out = o.g; a.lu_out = o.u; a.lpm_out = o.pm; a.lmm_out = o.mm;
+  HIPCHK(adj_launch(h, ADJ_SEED, a), "adjoint seed");
+  return NPHASE_OK;
+}
+
+int nphase_lbm_adjoint_step(nphase_lbm_t h, const void* fwd_state_dev, const void* adj_in_dev,
+                            void* adj_out_dev, void* adj_ws_dev, size_t adj_ws_bytes) {
+  int rc = adj_check(h);
+  if (rc) return rc;
+  if (!fwd_state_dev || !adj_in_dev || !adj_out_dev || !adj_ws_dev) {
+    h->err = "NULL pointer";
+    return NPHASE_EINVAL;
+  }
+  if (adj_in_dev == adj_out_dev) { h->err = "adjoint input and output must differ"; return NPHASE_EINVAL; }
+  if (adj_ws_bytes < adj_layout(h).total) { h->err = "adjoint workspace too small"; return NPHASE_ENOMEM; }
+  AdjArgs a = adj_args(h, adj_ws_dev);
+  const StatePtrs s = state_ptrs(h, fwd_state_dev);
+  const StatePtrs li = state_ptrs(h, adj_in_dev);
+  const StatePtrs lo = state_ptrs(h, adj_out_dev);
+  a.f = s.f; a.g = s.g; a.um = s.u; a.pm = s.pm; a.mm = s.mm;
+  a.lf_in = li.f; a.lg_in = li.g; a.lu_in = li.u; a.lpm_in = li.pm; a.lmm_in = li.mm;
+  a.lf_out = lo.f; a.lg_out = lo.g; a.lu_out = lo.u; a.lpm_out = lo.pm; a.lmm_out = lo.mm;
+  for (int which : {ADJ_FWD1, ADJ_FWD2, ADJ_FWD3, ADJ_REV1, ADJ_REV2, ADJ_REV3})
+    HIPCHK(adj_launch(h, which, a), "adjoint step");
+  return NPHASE_OK;
+}
+
+int nphase_lbm_adjoint_sigma(nphase_lbm_t h, void* adj_ws_dev, double* dL_dsigma_host, int reset) {
+  int rc = adj_check(h);
+  if (rc) return rc;
+  if (!adj_ws_dev) { h->err = "NULL workspace"; return NPHASE_EINVAL; }
+  const AdjLayout L = adj_layout(h);
+  const int N = h->N, NP = N * (N - 1) / 2;
+  double* part = (double*)((char*)adj_ws_dev + L.sig);
+  if (dL_dsigma_host) {
+    std::vector<double> host((size_t)(NP > 0 ? NP : 1) * L.nblk);
+    HIPCHK(hipMemcpyAsync(host.data(), part, host.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream), "sigma copy");
+    HIPCHK(hipStreamSynchronize(h->stream), "sigma sync");
+    for (int i = 0; i < NPHASE_MAX_N * NPHASE_MAX_N; ++i) dL_dsigma_host[i] = 0.0;
+    int k = 0;
+    for (int p = 0; p < N; ++p)
+      for (int q = p + 1; q < N; ++q, ++k) {
+        double acc = 0.0;
+        for (int b = 0; b < L.nblk; ++b) acc += host[(size_t)k * L.nblk + b];
+        dL_dsigma_host[p * NPHASE_MAX_N + q] = acc;
+        dL_dsigma_host[q * NPHASE_MAX_N + p] = acc;
+      }
+  }
+  if (reset) {
+    const long long n = (long long)(NP > 0 ? NP : 1) * L.nblk;
+    hipLaunchKernelGGL(zero_double_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->stream, part, n);
+    HIPCHK(hipGetLastError(), "sigma reset");
+  }
+  return NPHASE_OK;
+}
+
+int nphase_lbm_adjoint_init(nphase_lbm_t h, const void* adj_state_dev, double* dL_dphi0_dev) {
+  int rc = adj_check(h);
+  if (rc) return rc;
+  if (!adj_state_dev || !dL_dphi0_dev) { h->err = "NULL pointer"; return NPHASE_EINVAL; }
+  AdjArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.V = h->V; a.nx = h->prm.nx; a.ny = h->prm.ny; a.nz = h->prm.nz;
+  const StatePtrs li = state_ptrs(h, adj_state_dev);
+  a.lf_in = li.f; a.lpm_in = li.pm;
+  a.dphi0 = dL_dphi0_dev;
+  HIPCHK(adj_launch(h, ADJ_INIT, a), "adjoint init");
   return NPHASE_OK;
 }
 
