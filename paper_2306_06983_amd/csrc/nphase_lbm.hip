@@ -14,6 +14,7 @@
 #include "adjoint_dispatch.hpp"
 #include "aux_kernels.hpp"
 #include "dispatch.hpp"
+#include "step3d_kernel.hpp"
 
 using namespace nphase;
 
@@ -87,7 +88,8 @@ int validate(const nphase_lbm_params* p, std::string* why) {
   if (p->lattice != NPHASE_D2Q9 && p->lattice != NPHASE_D3Q19) return bad("unknown lattice");
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return bad("grid extents must be >= 1");
   if (p->lattice == NPHASE_D2Q9 && p->nz != 1) return bad("D2Q9 needs nz = 1");
-  if ((double)p->nx * p->ny * p->nz > 4.0e9) return bad("grid too large");
+  // node indices are 32-bit inside the kernels
+  if ((double)p->nx * p->ny * p->nz >= 4294967296.0) return bad("grid too large (>= 2^32 nodes)");
   if (p->n_phases < 2 || p->n_phases > NPHASE_MAX_N) return bad("n_phases out of [2, 8]");
   if (p->model != NPHASE_MODEL_A && p->model != NPHASE_MODEL_B) return bad("unknown model");
   if (p->model == NPHASE_MODEL_A && p->model_a_n < 1) return bad("model_a_n must be >= 1");
@@ -272,7 +274,7 @@ int nphase_lbm_create(const nphase_lbm_params* params, void* workspace_dev, size
   if (h->lat == NPHASE_D2Q9) {
     TX = TileShape<LAT_D2Q9>::TX; TY = TileShape<LAT_D2Q9>::TY; TZ = 1;
   } else {
-    TX = TileShape<LAT_D3Q19>::TX; TY = TileShape<LAT_D3Q19>::TY; TZ = TileShape<LAT_D3Q19>::TZ;
+    TX = Z3_TX; TY = Z3_TY; TZ = Z3_ZR;   // z-marching: columns x planes per workgroup
   }
   h->ntx = (params->nx + TX - 1) / TX;
   h->nty = (params->ny + TY - 1) / TY;

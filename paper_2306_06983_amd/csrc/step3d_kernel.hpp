@@ -1,0 +1,594 @@
+// Fused D3Q19 time step, z-marching variant.
+//
+// A workgroup of 256 threads owns a 16 x 16 column tile (one thread per column) and a run
+// of ZR planes in z.  It marches through the run with a three-stage pipeline, one plane
+// per stage and iteration:
+//   S1 plane z+2   phi (and Model B pair fractions) on the tile plus a 2-node ring in x,y,
+//                  into a ring of LDS planes (Sec. 3 macroscopic recovery);
+//   S2 plane z+1   gradients, Laplacians, sources R_p, m_phi on the tile plus a 1-node
+//                  ring, and the antisymmetric tensor m_phi u^- - u^- m_phi into a ring of
+//                  LDS planes (Sec. 2.1, Sec. 2.2, Sec. 3 closing paragraph);
+//   S3 plane z     correction force from that tensor, forces, u, P, the closed-form
+//                  moment-space collisions and push streaming (Sec. 2.2, Sec. 3).
+// The own-node results of S2 are kept in registers for the S3 of the next iteration, the
+// own column's first moments (and FP32 rounding residuals) in an LDS ring.  The
+// halo is recomputed only in x and y (1.56x the phi work for the 20 x 20 region plane, and
+// 1.27x the S2 work for the 18 x 18 inner plane); in z every plane is computed once per
+// run plus 4 pipeline-fill planes.  The arithmetic is the same as the tile kernel's.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lattice.hpp"
+#include "step_kernel.hpp"
+
+namespace nphase {
+
+constexpr int Z3_TX = 16, Z3_TY = 16;   // columns per workgroup
+constexpr int Z3_ZR = 32;               // planes per workgroup run
+
+template <typename T, int N, bool SA, int MODEL, int MODE>
+__global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 2 : 1) nphase_step3d_kernel(const StepArgs<T> a) {
+  using L = Lattice<LAT_D3Q19>;
+  constexpr int D = 3, Q = 19;
+  constexpr int NS = SA ? N : N - 1;
+  constexpr int NP = N * (N - 1) / 2;
+  constexpr bool DEV = sizeof(T) == 4;
+  constexpr int TX = Z3_TX, TY = Z3_TY, ZR = Z3_ZR;
+  constexpr int RX = TX + 4, RY = TY + 4, RP = RX * RY;   // region plane (2-node ring)
+  constexpr int IX = TX + 2, IY = TY + 2, IP = IX * IY;   // inner plane (1-node ring)
+  constexpr int PHR = DEV ? 5 : 3;                        // phi ring depth
+  constexpr int WR = 3;                                   // tensor ring depth
+  constexpr T CS2 = T(1) / T(3);
+  constexpr int JR = 3;   // own-moment ring depth (a barrier opens every iteration)
+  constexpr int NJ = NS * D + (DEV ? NS : 0);             // j_p (and FP32 residuals)
+  constexpr bool PF_LDS =
+      (MODEL == MODEL_B) &&
+      (sizeof(T) * ((NS * PHR + NP * 3) * RP + 3 * WR * IP + JR * NJ * NTHREADS) <= 81920);
+
+  __shared__ T s_phi[NS][PHR][RP];
+  __shared__ T s_j[JR][NJ][NTHREADS];   // first moments of the own column, read by S3
+  __shared__ T s_pf[PF_LDS ? NP : 1][PF_LDS ? 3 : 1][PF_LDS ? RP : 1];
+  __shared__ T s_w[3][WR][IP];
+
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const long long V = a.V;
+  const int t = threadIdx.x;
+
+  int tile;
+  {
+    const int b = blockIdx.x, nt = a.ntiles;
+    const int q = nt / 8, r8 = nt % 8, xcd = b % 8, loc = b / 8;
+    tile = xcd * q + (xcd < r8 ? xcd : r8) + loc;
+  }
+  const int tx0 = (tile % a.ntx) * TX;
+  const int ty0 = ((tile / a.ntx) % a.nty) * TY;
+  const int z0 = (tile / (a.ntx * a.nty)) * ZR;
+  const int zend = (z0 + ZR < nz) ? z0 + ZR : nz;   // collision planes [z0, zend)
+
+  const int lx = t % TX, ly = t / TX;
+  const int ox = tx0 + lx, oy = ty0 + ly;
+  const bool colvalid = (ox < nx) && (oy < ny);
+  const int rown = (lx + 2) + RX * (ly + 2);   // own column in the region plane
+  const int iown = (lx + 1) + IX * (ly + 1);   // own column in the inner plane
+  const int gxo = wrap(ox, nx), gyo = wrap(oy, ny);
+  const long long col_own = (long long)gxo + (long long)nx * gyo;
+  const long long plane = (long long)nx * ny;
+  // Element (component, node) of a [component][V] array as a uniform stream base plus a
+  // 32-bit node offset (node indices fit 32 bits: the host checks V < 2^32), so that one
+  // offset register serves all streams of a node.
+  const size_t Vs = (size_t)V;
+  auto LD = [&](const T* base, int comp, unsigned node) -> T {
+    return (base + (size_t)comp * Vs)[node];
+  };
+  auto ST = [&](T* base, int comp, unsigned node, T v) { (base + (size_t)comp * Vs)[node] = v; };
+
+  auto col_of = [&](int rx, int ry) -> long long {
+    return (long long)wrap(tx0 - 2 + rx, nx) + (long long)nx * wrap(ty0 - 2 + ry, ny);
+  };
+  auto ring_of = [&](int z, int R) { int r = z % R; return r < 0 ? r + R : r; };
+  auto roff2 = [&](int i) constexpr { return L::c(i, 0) + RX * L::c(i, 1); };
+  auto ioff2 = [&](int i) constexpr { return L::c(i, 0) + IX * L::c(i, 1); };
+
+  auto normalize = [&](T* v) {
+    T n2 = v[0] * v[0];
+#pragma unroll
+    for (int d = 1; d < D; ++d) n2 += v[d] * v[d];
+    if (n2 > T(NORMAL_EPS * NORMAL_EPS)) {
+      const T inv = T(1) / sqrt(n2);
+#pragma unroll
+      for (int d = 0; d < D; ++d) v[d] *= inv;
+    } else {
+#pragma unroll
+      for (int d = 0; d < D; ++d) v[d] = T(0);
+    }
+  };
+
+  // phi of all N phases at region node r of plane z
+  auto phi_at = [&](int r, int z, T* ph) {
+    const int sl = ring_of(z, PHR);
+#pragma unroll
+    for (int p = 0; p < NS; ++p) ph[p] = s_phi[p][sl][r];
+    if constexpr (!SA) {
+      T rest = ph[0];
+#pragma unroll
+      for (int p = 1; p < NS; ++p) rest += ph[p];
+      ph[N - 1] = T(1) - rest;
+    }
+  };
+
+  // ---- S1: phi (+ pair fractions) of one region-plane node of plane z
+  auto s1_node = [&](int r, long long col, int z, bool own) {
+    const unsigned gi = (unsigned)(col + plane * wrap(z, nz));
+    const int sl = ring_of(z, PHR);
+    const int jl = ring_of(z, JR);
+#pragma unroll
+    for (int p = 0; p < NS; ++p) {
+      T v[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) v[i] = LD(a.f_src, p * Q + i, gi);
+      T s = v[0];
+#pragma unroll
+      for (int i = 1; i < Q; ++i) s += v[i];
+      if constexpr (DEV) {
+        const T pm = LD(a.pm_src, p, gi);
+        const T sum = pm + s;
+        if (own) {
+          // two-sum residual of phi = phi^{t-1} + sum f~ (re-injected by S3)
+          const T bb = sum - pm;
+          s_j[jl][NS * D + p][t] = (pm - (sum - bb)) + (s - bb);
+        }
+        s = sum;
+      }
+      s_phi[p][sl][r] = s;
+      if (own) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          T jj = T(0);
+#pragma unroll
+          for (int i = 1; i < Q; ++i) {
+            if (L::c(i, d) == 1) jj += v[i];
+            if (L::c(i, d) == -1) jj -= v[i];
+          }
+          s_j[jl][p * D + d][t] = jj;
+        }
+      }
+    }
+    if constexpr (PF_LDS) {
+      T ph[N];
+      phi_at(r, z, ph);
+      int k = 0;
+#pragma unroll
+      for (int p = 0; p < N; ++p)
+#pragma unroll
+        for (int q = p + 1; q < N; ++q, ++k) s_pf[k][ring_of(z, 3)][r] = pair_fraction(ph[p], ph[q]);
+    }
+  };
+  auto s1_plane = [&](int z) {
+    s1_node(rown, col_own, z, true);
+    constexpr int NRING = RP - NTHREADS;
+    for (int k = t; k < NRING; k += NTHREADS) {
+      int rx, ry, rz;
+      ring_coord<2, RX, RY, 1>(k, rx, ry, rz);
+      s1_node(rx + RX * ry, col_of(rx, ry), z, false);
+    }
+  };
+
+  // ---- S2 at region node r of plane z: G, R (and L when lap), m_phi; returns via refs
+  auto s2_node = [&](int r, int z, bool lap, T (&G)[N][D], T (&Lp)[N], T (&R)[N][D],
+                     T (&phc)[N], T (&mphi)[D]) {
+    T H[(MODEL == MODEL_B) ? NP : 1][D];
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+      Lp[p] = T(0);
+#pragma unroll
+      for (int d = 0; d < D; ++d) G[p][d] = T(0);
+    }
+    if constexpr (MODEL == MODEL_B) {
+#pragma unroll
+      for (int k = 0; k < NP; ++k)
+#pragma unroll
+        for (int d = 0; d < D; ++d) H[k][d] = T(0);
+    }
+    phi_at(r, z, phc);
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      T ph[N];
+      const int rr = r + roff2(i), zz = z + L::c(i, 2);
+      phi_at(rr, zz, ph);
+      const T wg = T(3) * T(L::w(i));
+      const T wl = T(6) * T(L::w(i));
+#pragma unroll
+      for (int p = 0; p < N; ++p) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          if (L::c(i, d) == 1) G[p][d] += wg * ph[p];
+          if (L::c(i, d) == -1) G[p][d] -= wg * ph[p];
+        }
+        if (lap) Lp[p] += wl * (ph[p] - phc[p]);
+      }
+      if constexpr (MODEL == MODEL_B) {
+        int k = 0;
+#pragma unroll
+        for (int p = 0; p < N; ++p) {
+#pragma unroll
+          for (int q = p + 1; q < N; ++q, ++k) {
+            T v;
+            if constexpr (PF_LDS) v = s_pf[k][ring_of(zz, 3)][rr];
+            else v = pair_fraction(ph[p], ph[q]);
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+              if (L::c(i, d) == 1) H[k][d] += wg * v;
+              if (L::c(i, d) == -1) H[k][d] -= wg * v;
+            }
+          }
+        }
+      }
+    }
+    if constexpr (MODEL == MODEL_A) {
+      T an[D], pw[N], nv[N][D], ap[N];
+      T spw = T(0);
+#pragma unroll
+      for (int d = 0; d < D; ++d) an[d] = T(0);
+#pragma unroll
+      for (int p = 0; p < N; ++p) {
+        ap[p] = a.four_over_eps * phc[p] * (T(1) - phc[p]);
+#pragma unroll
+        for (int d = 0; d < D; ++d) nv[p][d] = G[p][d];
+        normalize(nv[p]);
+        T x = phc[p];
+        for (int k = 1; k < a.model_a_n; ++k) x *= phc[p];
+        pw[p] = x;
+        spw = (p == 0) ? x : spw + x;
+#pragma unroll
+        for (int d = 0; d < D; ++d) an[d] = (p == 0) ? ap[p] * nv[p][d] : an[d] + ap[p] * nv[p][d];
+      }
+#pragma unroll
+      for (int p = 0; p < N; ++p) {
+        const T lam = pw[p] / spw;
+#pragma unroll
+        for (int d = 0; d < D; ++d) R[p][d] = ap[p] * nv[p][d] - lam * an[d];
+      }
+    } else {
+#pragma unroll
+      for (int p = 0; p < N; ++p)
+#pragma unroll
+        for (int d = 0; d < D; ++d) R[p][d] = T(0);
+      int k = 0;
+#pragma unroll
+      for (int p = 0; p < N; ++p) {
+#pragma unroll
+        for (int q = p + 1; q < N; ++q, ++k) {
+          normalize(H[k]);
+          const T coef = a.four_over_eps * phc[p] * phc[q];
+#pragma unroll
+          for (int d = 0; d < D; ++d) {
+            R[p][d] += coef * H[k][d];
+            R[q][d] += coef * (-H[k][d]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      T acc = a.rho[0] * (G[0][d] - R[0][d]);
+#pragma unroll
+      for (int p = 1; p < N; ++p) acc += a.rho[p] * (G[p][d] - R[p][d]);
+      mphi[d] = -a.mob * acc;
+    }
+  };
+  auto store_w = [&](int iq, int z, long long gi64, const T (&mphi)[D]) {
+    const unsigned gi = (unsigned)gi64;
+    T um[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) um[d] = LD(a.u_src, d, gi);
+    const int sl = ring_of(z, WR);
+    s_w[0][sl][iq] = mphi[0] * um[1] - um[0] * mphi[1];
+    s_w[1][sl][iq] = mphi[0] * um[2] - um[0] * mphi[2];
+    s_w[2][sl][iq] = mphi[1] * um[2] - um[1] * mphi[2];
+  };
+
+  // Own-node S2 results reduced to what the collision stage needs: the surface tension
+  // F_s = sum_p mu_phi_p grad phi_p, grad rho, R_p of the evolved sets and m_phi.
+  // Produced for plane z+1, consumed by S3 of that plane one iteration later.
+  T Fsn[D], grn[D], Rn[NS][D], mpn[D];   // newest (plane zs2)
+  T Fsc[D], grc[D], Rc[NS][D], mpc[D];   // current (plane zs3)
+
+  for (int k = 0; k <= (zend - z0) + 3; ++k) {
+    const int zs1 = z0 - 2 + k;
+    const int zs2 = zs1 - 1;
+    const int zs3 = zs2 - 1;
+    // the previous iteration's S3 has read the ring slot this S1 overwrites
+    __syncthreads();
+    // S1 (planes z0-2 .. zend+1)
+    if (zs1 <= zend + 1) s1_plane(zs1);
+    __syncthreads();
+    // hand the previous S2 results to S3
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      Fsc[d] = Fsn[d];
+      grc[d] = grn[d];
+      mpc[d] = mpn[d];
+#pragma unroll
+      for (int p = 0; p < NS; ++p) Rc[p][d] = Rn[p][d];
+    }
+    // S2 (planes z0-1 .. zend)
+    if (zs2 >= z0 - 1 && zs2 <= zend) {
+      constexpr int NIRING = IP - NTHREADS;
+      T G[N][D], Lp[N], R[N][D], phc[N], mphi[D];
+      for (int kk = t; kk < NIRING; kk += NTHREADS) {
+        int ix, iy, iz;
+        ring_coord<1, IX, IY, 1>(kk, ix, iy, iz);
+        const int r = (ix + 1) + RX * (iy + 1);
+        s2_node(r, zs2, false, G, Lp, R, phc, mphi);
+        store_w(ix + IX * iy, zs2, col_of(ix + 1, iy + 1) + plane * wrap(zs2, nz), mphi);
+      }
+      {
+        s2_node(rown, zs2, true, G, Lp, R, phc, mpn);
+        store_w(iown, zs2, col_own + plane * wrap(zs2, nz), mpn);
+        // chemical potentials and the potential-form surface tension (Sec. 2.2)
+        T gp[N];
+#pragma unroll
+        for (int p = 0; p < N; ++p) gp[p] = gprime(phc[p]);
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          Fsn[d] = T(0);
+          grn[d] = a.rho[0] * G[0][d];
+        }
+#pragma unroll
+        for (int p = 1; p < N; ++p)
+#pragma unroll
+          for (int d = 0; d < D; ++d) grn[d] += a.rho[p] * G[p][d];
+#pragma unroll
+        for (int p = 0; p < N; ++p) {
+          T mu_p = T(0);
+#pragma unroll
+          for (int q = 0; q < N; ++q)
+            if (q != p) mu_p += a.beta2[p * MAXN + q] * (gp[p] - gprime(phc[p] + phc[q]));
+#pragma unroll
+          for (int q = 0; q < N; ++q)
+            if (q != p) mu_p -= a.kappa[p * MAXN + q] * Lp[q];
+#pragma unroll
+          for (int d = 0; d < D; ++d) Fsn[d] += mu_p * G[p][d];
+        }
+#pragma unroll
+        for (int p = 0; p < NS; ++p)
+#pragma unroll
+          for (int d = 0; d < D; ++d) Rn[p][d] = R[p][d];
+      }
+    }
+    __syncthreads();
+    // S3 (planes z0 .. zend-1)
+    if (zs3 < z0 || zs3 >= zend || !colvalid) continue;
+    const unsigned g_own = (unsigned)(col_own + plane * zs3);
+
+    // phi^{t-1} of the evolved sets
+    T phm[N];
+#pragma unroll
+    for (int p = 0; p < NS; ++p) phm[p] = LD(a.pm_src, p, g_own);
+    if constexpr (!SA) {
+      T rest = phm[0];
+#pragma unroll
+      for (int p = 1; p < NS; ++p) rest += phm[p];
+      phm[N - 1] = T(1) - rest;
+    }
+
+    // correction force from the tensor ring
+    T Fc[D];
+    {
+      T DW[3][D];
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+        for (int d = 0; d < D; ++d) DW[kk][d] = T(0);
+#pragma unroll
+      for (int i = 1; i < Q; ++i) {
+        const T wg = T(3) * T(L::w(i));
+        const int sl = ring_of(zs3 + L::c(i, 2), WR);
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) {
+          const T v = s_w[kk][sl][iown + ioff2(i)];
+#pragma unroll
+          for (int d = 0; d < D; ++d) {
+            if (L::c(i, d) == 1) DW[kk][d] += wg * v;
+            if (L::c(i, d) == -1) DW[kk][d] -= wg * v;
+          }
+        }
+      }
+      Fc[0] = T(0.5) * (DW[0][1] + DW[1][2]);
+      Fc[1] = T(-0.5) * DW[0][0] + T(0.5) * DW[2][2];
+      Fc[2] = T(-0.5) * (DW[1][0] + DW[2][1]);
+    }
+
+    T phi_own[N];
+    phi_at(rown, zs3, phi_own);
+    T rho = a.rho[0] * phi_own[0], mu = a.mu[0] * phi_own[0];
+#pragma unroll
+    for (int p = 1; p < N; ++p) {
+      rho += a.rho[p] * phi_own[p];
+      mu += a.mu[p] * phi_own[p];
+    }
+    const T tau_g = T(0.5) + mu / (rho * CS2);
+    const T s2 = T(1) / tau_g;
+
+    T F[D], grho[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      grho[d] = grc[d];
+      F[d] = Fsc[d] + (rho - a.rho_bar) * a.grav[d] + Fc[d];
+    }
+
+    T gv[Q];
+    gv[0] = T(0);
+#pragma unroll
+    for (int i = 1; i < Q; ++i) gv[i] = LD(a.g_src, i - 1, g_own);
+    T jg[D], Pi[D][D], sumg = T(0);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      jg[d] = T(0);
+#pragma unroll
+      for (int e = 0; e < D; ++e) Pi[d][e] = T(0);
+    }
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      sumg += gv[i];
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        if (L::c(i, d) == 1) jg[d] += gv[i];
+        if (L::c(i, d) == -1) jg[d] -= gv[i];
+#pragma unroll
+        for (int e = 0; e < D; ++e)
+          if (L::c(i, d) * L::c(i, e) == 1) Pi[d][e] += gv[i];
+          else if (L::c(i, d) * L::c(i, e) == -1) Pi[d][e] -= gv[i];
+      }
+    }
+    T u[D], m[D], um[D], mm_prev[D];
+    const T inv_rho = T(1) / rho;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      u[d] = (jg[d] + T(0.5) * F[d]) * inv_rho;
+      m[d] = rho * u[d] + mpc[d];
+      um[d] = LD(a.u_src, d, g_own);
+      mm_prev[d] = LD(a.mm, d, g_own);
+    }
+    T rho_prev = a.rho[0] * phm[0];
+#pragma unroll
+    for (int p = 1; p < N; ++p) rho_prev += a.rho[p] * phm[p];
+    T mu_dot = m[0] * u[0], mu_prev = (rho_prev * um[0] + mm_prev[0]) * um[0], ugr = u[0] * grho[0];
+#pragma unroll
+    for (int d = 1; d < D; ++d) {
+      mu_dot += m[d] * u[d];
+      mu_prev += (rho_prev * um[d] + mm_prev[d]) * um[d];
+      ugr += u[d] * grho[d];
+    }
+    constexpr T w0 = T(L::w(0));
+    const T P = CS2 / (T(1) - w0) *
+                (sumg + T(0.5) * ugr - w0 * mu_dot / (T(2) * CS2) +
+                 w0 * T(0.5) * (mu_dot - mu_prev) / (T(2) * CS2));
+
+    if constexpr (MODE == MODE_FIELDS) {
+      if (a.phi_out) {
+#pragma unroll
+        for (int p = 0; p < N; ++p) a.phi_out[(size_t)p * Vs + g_own] = (double)phi_own[p];
+      }
+      if (a.u_out) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) a.u_out[(size_t)d * Vs + g_own] = (double)u[d];
+      }
+      if (a.p_out) a.p_out[g_own] = (double)P;
+    } else {
+      int X[3], Y[3], Z[3];
+      X[0] = wrap(ox - 1, nx); X[1] = ox; X[2] = wrap(ox + 1, nx);
+      Y[0] = wrap(oy - 1, ny); Y[1] = oy; Y[2] = wrap(oy + 1, ny);
+      Z[0] = wrap(zs3 - 1, nz); Z[1] = zs3; Z[2] = wrap(zs3 + 1, nz);
+      auto dest = [&](int i) -> unsigned {
+        return (unsigned)X[L::c(i, 0) + 1] +
+               (unsigned)nx * ((unsigned)Y[L::c(i, 1) + 1] + (unsigned)ny * (unsigned)Z[L::c(i, 2) + 1]);
+      };
+#pragma unroll
+      for (int p = 0; p < NS; ++p) {
+        const T ph = phi_own[p];
+        // first moment j_p of the own populations and the FP32 residual, from S1
+        T j_own[D], res_own = T(0);
+        const int jl = ring_of(zs3, JR);
+#pragma unroll
+        for (int d = 0; d < D; ++d) j_own[d] = s_j[jl][p * D + d][t];
+        if constexpr (DEV) res_own = s_j[jl][NS * D + p][t];
+        T Zp[D], A[D], Dp[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          Zp[d] = T(3) * (ph * u[d] - phm[p] * um[d]) + Rc[p][d];
+          A[d] = T(3) * ph * u[d] + T(0.5) * Zp[d];
+          Dp[d] = (T(1) - a.s1) * (j_own[d] - ph * u[d] + T(0.5) * CS2 * Zp[d]);
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          T cA = T(0), cD = T(0);
+#pragma unroll
+          for (int d = 0; d < D; ++d) {
+            if (L::c(i, d) == 1) { cA += A[d]; cD += Dp[d]; }
+            if (L::c(i, d) == -1) { cA -= A[d]; cD -= Dp[d]; }
+          }
+          const T wi = T(L::w(i));
+          T fs;
+          if constexpr (DEV) {
+            if (i == 0) {
+              fs = wi * cA + res_own;
+            } else {
+              const T dphi =
+                  ph - s_phi[p][ring_of(zs3 + L::c(i, 2), PHR)][rown + roff2(i)];
+              fs = wi * (dphi + cA);
+            }
+          } else {
+            fs = wi * (ph + cA);
+          }
+          if (cnorm2<L>(i) == 1) fs += T(0.5) * cD;
+          ST(a.f_dst, p * Q + i, dest(i), fs);
+        }
+        ST(a.pm_dst, p, g_own, ph);
+      }
+      T T2[D][D];
+      T trT = T(0);
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+#pragma unroll
+        for (int e = 0; e < D; ++e)
+          T2[d][e] = u[d] * F[e] + F[d] * u[e] +
+                     T(0.5) * ((mpc[d] * u[e] + u[d] * mpc[e]) -
+                               (mm_prev[d] * um[e] + um[d] * mm_prev[e])) +
+                     CS2 * (u[d] * grho[e] + grho[d] * u[e]);
+        trT += T2[d][d];
+      }
+      T Nn[D][D];
+#pragma unroll
+      for (int d = 0; d < D; ++d)
+#pragma unroll
+        for (int e = 0; e < D; ++e) {
+          const T eq = ((d == e) ? P : T(0)) + T(0.5) * (m[d] * u[e] + m[e] * u[d]);
+          const T m2f = T2[d][e] + ((d == e) ? CS2 * ugr : T(0));
+          Nn[d][e] = Pi[d][e] - eq + T(0.5) * m2f;
+        }
+      const T oms2 = T(1) - s2;
+#pragma unroll
+      for (int i = 1; i < Q; ++i) {
+        T cu = T(0), cm = T(0), cF = T(0), cTc = T(0);
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          const int cd = L::c(i, d);
+          if (cd != 0) {
+            cu += T(cd) * u[d];
+            cm += T(cd) * m[d];
+            cF += T(cd) * F[d];
+#pragma unroll
+            for (int e = 0; e < D; ++e)
+              if (L::c(i, e) != 0) cTc += T(cd * L::c(i, e)) * T2[d][e];
+          }
+        }
+        const T wi = T(L::w(i));
+        const T geq = wi * (T(3) * P + T(3) * rho * cu + T(4.5) * cm * cu - T(1.5) * mu_dot);
+        const T Fi = wi * (ugr + T(3) * cF + T(4.5) * (cTc - CS2 * trT));
+        T corr = T(0);
+        if (cnorm2<L>(i) == 1) {
+#pragma unroll
+          for (int d = 0; d < D; ++d)
+            if (L::c(i, d) != 0) corr = T(0.5) * Nn[d][d];
+        } else {
+#pragma unroll
+          for (int d = 0; d < D; ++d)
+#pragma unroll
+            for (int e = d + 1; e < D; ++e)
+              if (L::c(i, d) != 0 && L::c(i, e) != 0)
+                corr = T(0.25) * T(L::c(i, d) * L::c(i, e)) * Nn[d][e];
+        }
+        ST(a.g_dst, i - 1, dest(i), geq + T(0.5) * Fi + oms2 * corr);
+      }
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        ST(a.u_dst, d, g_own, u[d]);
+        ST(a.mm, d, g_own, mpc[d]);
+      }
+    }
+  }
+}
+
+}  // namespace nphase

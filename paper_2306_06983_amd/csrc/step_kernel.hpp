@@ -81,9 +81,9 @@ struct TileShape<LAT_D2Q9> {
   static constexpr int TX = 32, TY = 8, TZ = 1;
 };
 template <>
-struct TileShape<LAT_D3Q19> {
-  static constexpr int TX = 8, TY = 8, TZ = 4;
-};
+struct TileShape<LAT_D3Q19> {   // used by the tile kernel only if instantiated for D3Q19;
+  static constexpr int TX = 8, TY = 8, TZ = 4;   // the library runs D3Q19 on the
+};                                                 // z-marching kernel (step3d_kernel.hpp)
 
 __device__ __forceinline__ int wrap(int v, int n) {
   int r = v % n;
@@ -188,6 +188,15 @@ __global__ void __launch_bounds__(NTHREADS) nphase_step_kernel(const StepArgs<T>
   const int ty0 = ((tile / a.ntx) % a.nty) * TY;
   const int tz0 = (tile / (a.ntx * a.nty)) * TZ;
 
+  // Element (component, node) of a [component][V] array as a uniform stream base plus a
+  // 32-bit node offset (the host checks V < 2^32): one offset register per node serves
+  // every stream instead of one 64-bit address per stream.
+  const size_t Vs = (size_t)V;
+  auto LD = [&](const T* base, int comp, unsigned node) -> T {
+    return (base + (size_t)comp * Vs)[node];
+  };
+  auto ST = [&](T* base, int comp, unsigned node, T v) { (base + (size_t)comp * Vs)[node] = v; };
+
   auto region_gidx = [&](int rx, int ry, int rz) -> long long {
     const int gx = wrap(tx0 - 2 + rx, nx);
     const int gy = wrap(ty0 - 2 + ry, ny);
@@ -217,12 +226,12 @@ __global__ void __launch_bounds__(NTHREADS) nphase_step_kernel(const StepArgs<T>
     for (int p = 0; p < NS; ++p) {
       T v[Q];
 #pragma unroll
-      for (int i = 0; i < Q; ++i) v[i] = a.f_src[(long long)(p * Q + i) * V + gi];
+      for (int i = 0; i < Q; ++i) v[i] = LD(a.f_src, p * Q + i, (unsigned)gi);
       T s = v[0];
 #pragma unroll
       for (int i = 1; i < Q; ++i) s += v[i];
       if constexpr (DEV) {
-        const T pm = a.pm_src[(long long)p * V + gi];
+        const T pm = LD(a.pm_src, p, (unsigned)gi);
         const T sum = pm + s;
         if (own) {
           // two-sum: (pm + s) - sum exactly; it is re-injected into the rest deviation
@@ -411,7 +420,7 @@ __global__ void __launch_bounds__(NTHREADS) nphase_step_kernel(const StepArgs<T>
   auto store_w = [&](int iq, long long gi) {
     T um[D];
 #pragma unroll
-    for (int d = 0; d < D; ++d) um[d] = a.u_src[(long long)d * V + gi];
+    for (int d = 0; d < D; ++d) um[d] = LD(a.u_src, d, (unsigned)gi);
     s_w[0][iq] = mphi[0] * um[1] - um[0] * mphi[1];
     if constexpr (D == 3) {
       s_w[1][iq] = mphi[0] * um[2] - um[0] * mphi[2];
@@ -514,7 +523,7 @@ __global__ void __launch_bounds__(NTHREADS) nphase_step_kernel(const StepArgs<T>
   T gv[Q];
   gv[0] = T(0);
 #pragma unroll
-  for (int i = 1; i < Q; ++i) gv[i] = a.g_src[(long long)(i - 1) * V + g_own];
+  for (int i = 1; i < Q; ++i) gv[i] = LD(a.g_src, i - 1, (unsigned)g_own);
   T jg[D], Pi[D][D], sumg = T(0);
 #pragma unroll
   for (int d = 0; d < D; ++d) {
@@ -541,14 +550,14 @@ __global__ void __launch_bounds__(NTHREADS) nphase_step_kernel(const StepArgs<T>
   for (int d = 0; d < D; ++d) {
     u[d] = (jg[d] + T(0.5) * F[d]) * inv_rho;
     m[d] = rho * u[d] + mphi[d];
-    um[d] = a.u_src[(long long)d * V + g_own];
-    mm_prev[d] = a.mm[(long long)d * V + g_own];
+    um[d] = LD(a.u_src, d, (unsigned)g_own);
+    mm_prev[d] = LD(a.mm, d, (unsigned)g_own);
   }
   T phm[N];
 #pragma unroll
   for (int p = 0; p < NS; ++p) {
     if constexpr (DEV) phm[p] = pm_own[p];
-    else phm[p] = a.pm_src[(long long)p * V + g_own];
+    else phm[p] = LD(a.pm_src, p, (unsigned)g_own);
   }
   if constexpr (!SA) {
     T rest = phm[0];
@@ -592,9 +601,9 @@ __global__ void __launch_bounds__(NTHREADS) nphase_step_kernel(const StepArgs<T>
     } else {
       Z[0] = Z[1] = Z[2] = 0;
     }
-    auto dest = [&](int i) -> long long {
-      return (long long)X[L::c(i, 0) + 1] +
-             (long long)nx * ((long long)Y[L::c(i, 1) + 1] + (long long)ny * Z[L::c(i, 2) + 1]);
+    auto dest = [&](int i) -> unsigned {
+      return (unsigned)X[L::c(i, 0) + 1] +
+             (unsigned)nx * ((unsigned)Y[L::c(i, 1) + 1] + (unsigned)ny * (unsigned)Z[L::c(i, 2) + 1]);
     };
 
     // ---- phase-field collision (closed form of f - M^-1 S M (f - f^eq) + (I - M^-1 S M/2) R)
@@ -632,9 +641,9 @@ __global__ void __launch_bounds__(NTHREADS) nphase_step_kernel(const StepArgs<T>
           fs = wi * (ph + cA);
         }
         if (cnorm2<L>(i) == 1) fs += T(0.5) * cD;
-        a.f_dst[(long long)(p * Q + i) * V + dest(i)] = fs;
+        ST(a.f_dst, p * Q + i, dest(i), fs);
       }
-      a.pm_dst[(long long)p * V + g_own] = ph;
+      ST(a.pm_dst, p, (unsigned)g_own, ph);
     }
 
     // ---- flow collision: g* = g^eq + F_i/2 + (1 - s2) M^-1 [second-order rows of
@@ -694,12 +703,12 @@ __global__ void __launch_bounds__(NTHREADS) nphase_step_kernel(const StepArgs<T>
             if (L::c(i, d) != 0 && L::c(i, e) != 0)
               corr = T(0.25) * T(L::c(i, d) * L::c(i, e)) * Nn[d][e];
       }
-      a.g_dst[(long long)(i - 1) * V + dest(i)] = geq + T(0.5) * Fi + oms2 * corr;
+      ST(a.g_dst, i - 1, dest(i), geq + T(0.5) * Fi + oms2 * corr);
     }
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      a.u_dst[(long long)d * V + g_own] = u[d];
-      a.mm[(long long)d * V + g_own] = mphi[d];
+      ST(a.u_dst, d, (unsigned)g_own, u[d]);
+      ST(a.mm, d, (unsigned)g_own, mphi[d]);
     }
   }
 }
