@@ -42,12 +42,18 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 2 : 1) nphase_step3
   constexpr T CS2 = T(1) / T(3);
   constexpr int JR = 3;   // own-moment ring depth (a barrier opens every iteration)
   constexpr int NJ = NS * D + (DEV ? NS : 0);             // j_p (and FP32 residuals)
+  // LDS budget: two workgroups per CU for FP32, one for FP64.  The own-moment ring is
+  // kept in LDS when it fits beside the plane rings (else the collision stage re-reads
+  // the own populations), then the Model B pair fractions (else recomputed per point).
+  constexpr int BUDGET = DEV ? 81920 : 162816;
+  constexpr int BASE = sizeof(T) * (NS * PHR * RP + 3 * WR * IP);
+  constexpr bool J_LDS = BASE + (int)sizeof(T) * JR * NJ * NTHREADS <= BUDGET;
+  constexpr int JB = J_LDS ? JR * NJ * NTHREADS : 0;
   constexpr bool PF_LDS =
-      (MODEL == MODEL_B) &&
-      (sizeof(T) * ((NS * PHR + NP * 3) * RP + 3 * WR * IP + JR * NJ * NTHREADS) <= 81920);
+      (MODEL == MODEL_B) && BASE + (int)sizeof(T) * (JB + NP * 3 * RP) <= BUDGET;
 
   __shared__ T s_phi[NS][PHR][RP];
-  __shared__ T s_j[JR][NJ][NTHREADS];   // first moments of the own column, read by S3
+  __shared__ T s_j[J_LDS ? JR : 1][J_LDS ? NJ : 1][J_LDS ? NTHREADS : 1];   // own moments
   __shared__ T s_pf[PF_LDS ? NP : 1][PF_LDS ? 3 : 1][PF_LDS ? RP : 1];
   __shared__ T s_w[3][WR][IP];
 
@@ -133,7 +139,7 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 2 : 1) nphase_step3
       if constexpr (DEV) {
         const T pm = LD(a.pm_src, p, gi);
         const T sum = pm + s;
-        if (own) {
+        if (J_LDS && own) {
           // two-sum residual of phi = phi^{t-1} + sum f~ (re-injected by S3)
           const T bb = sum - pm;
           s_j[jl][NS * D + p][t] = (pm - (sum - bb)) + (s - bb);
@@ -141,7 +147,7 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 2 : 1) nphase_step3
         s = sum;
       }
       s_phi[p][sl][r] = s;
-      if (own) {
+      if (J_LDS && own) {
 #pragma unroll
         for (int d = 0; d < D; ++d) {
           T jj = T(0);
@@ -490,10 +496,34 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 2 : 1) nphase_step3
         const T ph = phi_own[p];
         // first moment j_p of the own populations and the FP32 residual, from S1
         T j_own[D], res_own = T(0);
-        const int jl = ring_of(zs3, JR);
+        if constexpr (J_LDS) {
+          const int jl = ring_of(zs3, JR);
 #pragma unroll
-        for (int d = 0; d < D; ++d) j_own[d] = s_j[jl][p * D + d][t];
-        if constexpr (DEV) res_own = s_j[jl][NS * D + p][t];
+          for (int d = 0; d < D; ++d) j_own[d] = s_j[jl][p * D + d][t];
+          if constexpr (DEV) res_own = s_j[jl][NS * D + p][t];
+        } else {
+          T v[Q];
+#pragma unroll
+          for (int i = 0; i < Q; ++i) v[i] = LD(a.f_src, p * Q + i, g_own);
+#pragma unroll
+          for (int d = 0; d < D; ++d) {
+            T jj = T(0);
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+              if (L::c(i, d) == 1) jj += v[i];
+              if (L::c(i, d) == -1) jj -= v[i];
+            }
+            j_own[d] = jj;
+          }
+          if constexpr (DEV) {
+            T sf = v[0];
+#pragma unroll
+            for (int i = 1; i < Q; ++i) sf += v[i];
+            const T pm = phm[p];
+            const T sum = pm + sf, bb = sum - pm;
+            res_own = (pm - (sum - bb)) + (sf - bb);
+          }
+        }
         T Zp[D], A[D], Dp[D];
 #pragma unroll
         for (int d = 0; d < D; ++d) {
