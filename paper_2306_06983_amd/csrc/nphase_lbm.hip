@@ -32,6 +32,7 @@ struct nphase_lbm_s {
   void* u[2] = {nullptr, nullptr};
   void* pm[2] = {nullptr, nullptr};
   void* mm = nullptr;
+  void* mo = nullptr;   // D3Q19 moment scratch (not part of the state)
   double* partial = nullptr;
   double* mass_dev = nullptr;
   int* flag_dev = nullptr;
@@ -54,7 +55,7 @@ constexpr double CS2 = 1.0 / 3.0;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-  size_t f, g, u, pm, mm, partial, mass, flag, total;
+  size_t f, g, u, pm, mm, mo, partial, mass, flag, total;
 };
 
 // sizes of every buffer for a validated parameter set
@@ -71,10 +72,13 @@ Layout layout_of(const nphase_lbm_params& p) {
   L.u = align_up((size_t)D * V * ts);
   L.pm = align_up((size_t)NS * V * ts);
   L.mm = align_up((size_t)D * V * ts);
+  // D3Q19: per-node moments of the phase populations (phi, j, FP32 residual), rewritten
+  // by every step
+  L.mo = p.lattice == NPHASE_D3Q19 ? align_up((size_t)NS * (4 + (ts == 4 ? 1 : 0)) * V * ts) : 0;
   L.partial = align_up((size_t)MAXN * RED_BLOCKS * sizeof(double));
   L.mass = align_up(MAXN * sizeof(double));
   L.flag = align_up(sizeof(int) * 4);
-  L.total = 2 * (L.f + L.g + L.u + L.pm) + L.mm + L.partial + L.mass + L.flag;
+  L.total = 2 * (L.f + L.g + L.u + L.pm) + L.mm + L.mo + L.partial + L.mass + L.flag;
   return L;
 }
 
@@ -146,6 +150,7 @@ void fill_args(nphase_lbm_t h, StepArgs<T>* out) {
     a.pm_src = (const T*)h->pm[side];
     a.pm_dst = (T*)h->pm[dst];
     a.mm = (T*)h->mm;
+    a.mo = (T*)h->mo;
     a.nx = p.nx;
     a.ny = p.ny;
     a.nz = p.nz;
@@ -267,6 +272,7 @@ int nphase_lbm_create(const nphase_lbm_params* params, void* workspace_dev, size
   for (int s = 0; s < 2; ++s) { h->u[s] = q; q += L.u; }
   for (int s = 0; s < 2; ++s) { h->pm[s] = q; q += L.pm; }
   h->mm = q; q += L.mm;
+  h->mo = L.mo ? q : nullptr; q += L.mo;
   h->partial = (double*)q; q += L.partial;
   h->mass_dev = (double*)q; q += L.mass;
   h->flag_dev = (int*)q; q += L.flag;

@@ -1,20 +1,26 @@
-// Fused D3Q19 time step, z-marching variant.
+// D3Q19 time step: a moments pass and a fused z-marching collide-and-stream pass.
 //
-// A workgroup of 256 threads owns a 16 x 16 column tile (one thread per column) and a run
-// of ZR planes in z.  It marches through the run with a three-stage pipeline, one plane
-// per stage and iteration:
+// nphase_moments3d_kernel (one thread per node) reduces the post-stream phase populations
+// of every node to what the rest of the step uses of them (Sec. 3 macroscopic recovery):
+// phi_p = sum_i f_{i,p} and the first moments j_p = sum_i c_i f_{i,p}; FP32 also keeps the
+// exact rounding residual of phi = phi^{t-1} + sum f~.  Every later stage of the step uses
+// the populations only through these moments (the collisions are in closed form), so the
+// halo of the stencils reads 1 value per phase and node instead of Q.
+//
+// nphase_step3d_kernel: a workgroup of 256 threads owns a 16 x 16 column tile (one thread
+// per column) and a run of ZR planes in z.  It marches through the run with a three-stage
+// pipeline, one plane per stage and iteration:
 //   S1 plane z+2   phi (and Model B pair fractions) on the tile plus a 2-node ring in x,y,
-//                  into a ring of LDS planes (Sec. 3 macroscopic recovery);
+//                  from the moments, into a ring of LDS planes;
 //   S2 plane z+1   gradients, Laplacians, sources R_p, m_phi on the tile plus a 1-node
 //                  ring, and the antisymmetric tensor m_phi u^- - u^- m_phi into a ring of
 //                  LDS planes (Sec. 2.1, Sec. 2.2, Sec. 3 closing paragraph);
 //   S3 plane z     correction force from that tensor, forces, u, P, the closed-form
 //                  moment-space collisions and push streaming (Sec. 2.2, Sec. 3).
-// The own-node results of S2 are kept in registers for the S3 of the next iteration, the
-// own column's first moments (and FP32 rounding residuals) in an LDS ring.  The
-// halo is recomputed only in x and y (1.56x the phi work for the 20 x 20 region plane, and
-// 1.27x the S2 work for the 18 x 18 inner plane); in z every plane is computed once per
-// run plus 4 pipeline-fill planes.  The arithmetic is the same as the tile kernel's.
+// The own-node results of S2 are kept in registers for the S3 of the next iteration.  The
+// halo is recomputed only in x and y (1.56x the phi loads for the 20 x 20 region plane,
+// and 1.27x the S2 work for the 18 x 18 inner plane); in z every plane is computed once
+// per run plus 4 pipeline-fill planes.  The arithmetic is the same as the tile kernel's.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -26,6 +32,53 @@ namespace nphase {
 
 constexpr int Z3_TX = 16, Z3_TY = 16;   // columns per workgroup
 constexpr int Z3_ZR = 32;               // planes per workgroup run
+
+// Moments of one node, layout mo[NM][V]: [p] phi_p, [NS + p D + d] j_{p,d}, and for FP32
+// [NS + NS D + p] the two-sum residual (phi^{t-1} + sum f~) - phi of the rounded phi.
+template <typename T, int NS>
+constexpr int n_moments() {
+  return NS * 4 + (sizeof(T) == 4 ? NS : 0);
+}
+
+template <typename T, int NS>
+__global__ void __launch_bounds__(NTHREADS) nphase_moments3d_kernel(const StepArgs<T> a) {
+  using L = Lattice<LAT_D3Q19>;
+  constexpr int D = 3, Q = 19;
+  constexpr bool DEV = sizeof(T) == 4;
+  const size_t Vs = (size_t)a.V;
+  const size_t gl = (size_t)blockIdx.x * NTHREADS + threadIdx.x;
+  if (gl >= Vs) return;
+  const unsigned gi = (unsigned)gl;
+  auto LD = [&](const T* base, int comp) -> T { return (base + (size_t)comp * Vs)[gi]; };
+  auto ST = [&](T* base, int comp, T v) { (base + (size_t)comp * Vs)[gi] = v; };
+#pragma unroll
+  for (int p = 0; p < NS; ++p) {
+    T v[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) v[i] = LD(a.f_src, p * Q + i);
+    T s = v[0];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) s += v[i];
+    if constexpr (DEV) {
+      const T pm = LD(a.pm_src, p);
+      const T sum = pm + s;
+      const T bb = sum - pm;
+      ST(a.mo, NS * (1 + D) + p, (pm - (sum - bb)) + (s - bb));
+      s = sum;
+    }
+    ST(a.mo, p, s);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      T jj = T(0);
+#pragma unroll
+      for (int i = 1; i < Q; ++i) {
+        if (L::c(i, d) == 1) jj += v[i];
+        if (L::c(i, d) == -1) jj -= v[i];
+      }
+      ST(a.mo, NS + p * D + d, jj);
+    }
+  }
+}
 
 template <typename T, int N, bool SA, int MODEL, int MODE>
 __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 2 : 1) nphase_step3d_kernel(const StepArgs<T> a) {
@@ -40,20 +93,13 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 2 : 1) nphase_step3
   constexpr int PHR = DEV ? 5 : 3;                        // phi ring depth
   constexpr int WR = 3;                                   // tensor ring depth
   constexpr T CS2 = T(1) / T(3);
-  constexpr int JR = 3;   // own-moment ring depth (a barrier opens every iteration)
-  constexpr int NJ = NS * D + (DEV ? NS : 0);             // j_p (and FP32 residuals)
-  // LDS budget: two workgroups per CU for FP32, one for FP64.  The own-moment ring is
-  // kept in LDS when it fits beside the plane rings (else the collision stage re-reads
-  // the own populations), then the Model B pair fractions (else recomputed per point).
+  // LDS budget: two workgroups per CU for FP32, one for FP64; the Model B pair fractions
+  // are staged when they fit, else recomputed at every stencil point.
   constexpr int BUDGET = DEV ? 81920 : 162816;
   constexpr int BASE = sizeof(T) * (NS * PHR * RP + 3 * WR * IP);
-  constexpr bool J_LDS = BASE + (int)sizeof(T) * JR * NJ * NTHREADS <= BUDGET;
-  constexpr int JB = J_LDS ? JR * NJ * NTHREADS : 0;
-  constexpr bool PF_LDS =
-      (MODEL == MODEL_B) && BASE + (int)sizeof(T) * (JB + NP * 3 * RP) <= BUDGET;
+  constexpr bool PF_LDS = (MODEL == MODEL_B) && BASE + (int)sizeof(T) * NP * 3 * RP <= BUDGET;
 
   __shared__ T s_phi[NS][PHR][RP];
-  __shared__ T s_j[J_LDS ? JR : 1][J_LDS ? NJ : 1][J_LDS ? NTHREADS : 1];   // own moments
   __shared__ T s_pf[PF_LDS ? NP : 1][PF_LDS ? 3 : 1][PF_LDS ? RP : 1];
   __shared__ T s_w[3][WR][IP];
 
@@ -124,42 +170,11 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 2 : 1) nphase_step3
   };
 
   // ---- S1: phi (+ pair fractions) of one region-plane node of plane z
-  auto s1_node = [&](int r, long long col, int z, bool own) {
+  auto s1_node = [&](int r, long long col, int z) {
     const unsigned gi = (unsigned)(col + plane * wrap(z, nz));
     const int sl = ring_of(z, PHR);
-    const int jl = ring_of(z, JR);
 #pragma unroll
-    for (int p = 0; p < NS; ++p) {
-      T v[Q];
-#pragma unroll
-      for (int i = 0; i < Q; ++i) v[i] = LD(a.f_src, p * Q + i, gi);
-      T s = v[0];
-#pragma unroll
-      for (int i = 1; i < Q; ++i) s += v[i];
-      if constexpr (DEV) {
-        const T pm = LD(a.pm_src, p, gi);
-        const T sum = pm + s;
-        if (J_LDS && own) {
-          // two-sum residual of phi = phi^{t-1} + sum f~ (re-injected by S3)
-          const T bb = sum - pm;
-          s_j[jl][NS * D + p][t] = (pm - (sum - bb)) + (s - bb);
-        }
-        s = sum;
-      }
-      s_phi[p][sl][r] = s;
-      if (J_LDS && own) {
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-          T jj = T(0);
-#pragma unroll
-          for (int i = 1; i < Q; ++i) {
-            if (L::c(i, d) == 1) jj += v[i];
-            if (L::c(i, d) == -1) jj -= v[i];
-          }
-          s_j[jl][p * D + d][t] = jj;
-        }
-      }
-    }
+    for (int p = 0; p < NS; ++p) s_phi[p][sl][r] = LD(a.mo, p, gi);
     if constexpr (PF_LDS) {
       T ph[N];
       phi_at(r, z, ph);
@@ -171,12 +186,12 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 2 : 1) nphase_step3
     }
   };
   auto s1_plane = [&](int z) {
-    s1_node(rown, col_own, z, true);
+    s1_node(rown, col_own, z);
     constexpr int NRING = RP - NTHREADS;
     for (int k = t; k < NRING; k += NTHREADS) {
       int rx, ry, rz;
       ring_coord<2, RX, RY, 1>(k, rx, ry, rz);
-      s1_node(rx + RX * ry, col_of(rx, ry), z, false);
+      s1_node(rx + RX * ry, col_of(rx, ry), z);
     }
   };
 
@@ -304,8 +319,8 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 2 : 1) nphase_step3
     const int zs1 = z0 - 2 + k;
     const int zs2 = zs1 - 1;
     const int zs3 = zs2 - 1;
-    // the previous iteration's S3 has read the ring slot this S1 overwrites
-    __syncthreads();
+    // with a 3-plane phi ring this S1 overwrites the plane the previous S3 read
+    if constexpr (PHR < 4) __syncthreads();
     // S1 (planes z0-2 .. zend+1)
     if (zs1 <= zend + 1) s1_plane(zs1);
     __syncthreads();
@@ -494,36 +509,11 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 2 : 1) nphase_step3
 #pragma unroll
       for (int p = 0; p < NS; ++p) {
         const T ph = phi_own[p];
-        // first moment j_p of the own populations and the FP32 residual, from S1
+        // first moment j_p of the own populations and the FP32 residual
         T j_own[D], res_own = T(0);
-        if constexpr (J_LDS) {
-          const int jl = ring_of(zs3, JR);
 #pragma unroll
-          for (int d = 0; d < D; ++d) j_own[d] = s_j[jl][p * D + d][t];
-          if constexpr (DEV) res_own = s_j[jl][NS * D + p][t];
-        } else {
-          T v[Q];
-#pragma unroll
-          for (int i = 0; i < Q; ++i) v[i] = LD(a.f_src, p * Q + i, g_own);
-#pragma unroll
-          for (int d = 0; d < D; ++d) {
-            T jj = T(0);
-#pragma unroll
-            for (int i = 1; i < Q; ++i) {
-              if (L::c(i, d) == 1) jj += v[i];
-              if (L::c(i, d) == -1) jj -= v[i];
-            }
-            j_own[d] = jj;
-          }
-          if constexpr (DEV) {
-            T sf = v[0];
-#pragma unroll
-            for (int i = 1; i < Q; ++i) sf += v[i];
-            const T pm = phm[p];
-            const T sum = pm + sf, bb = sum - pm;
-            res_own = (pm - (sum - bb)) + (sf - bb);
-          }
-        }
+        for (int d = 0; d < D; ++d) j_own[d] = LD(a.mo, NS + p * D + d, g_own);
+        if constexpr (DEV) res_own = LD(a.mo, NS * (1 + D) + p, g_own);
         T Zp[D], A[D], Dp[D];
 #pragma unroll
         for (int d = 0; d < D; ++d) {

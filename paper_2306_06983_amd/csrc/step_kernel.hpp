@@ -56,6 +56,7 @@ struct StepArgs {
   const T* pm_src;
   T* pm_dst;
   T* mm;
+  T* mo;             // D3Q19: per-node moments of the phase populations [NM][V]
   double* phi_out;   // fields mode: [N][V]
   double* u_out;     // fields mode: [D][V]
   double* p_out;     // fields mode: [V]
