@@ -1,6 +1,7 @@
 """Benchmark of the fused N-phase LBM step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
+    python bench.py --only spheres_fp64|spheres_fp32|bands_fp32 [--steps K] [--warmup W]
 
 Workload: 512 x 512 periodic D2Q9, N = 4 phases, 40 seeded non-overlapping discs radii
 U[10, 30] in an ambient phase, densities 1:2:3:4, sigma_pq U[0.005, 0.02], Model B
@@ -9,8 +10,11 @@ time step of every phase-field set and the flow set over the whole grid (one ker
 launch), inputs resident in HBM.  Prints ONE JSON line.
 
 value = FP64 Model B MLUPS (node updates per second / 1e6); the FP32 form, Model A and
-the oracle on the host (cpu_baseline) are reported beside it.  roofline: the step
-kernel is HBM-bound (no dense contraction); achieved = algorithmic bytes per launch
+the oracle on the host (cpu_baseline) are reported beside it, and (unless --no-extra)
+the 256^3 D3Q19 N = 4 drops (FP64, FP32), the 2048^2 N = 5 layered bands (FP32) and the
+wall time of a differentiable 256^2 run (forward with checkpoints, adjoint backward).
+`--only NAME` times one of those other workloads alone (for profiling) and prints its
+record instead of the line.  roofline: the step kernel is HBM-bound (no dense contraction); achieved = algorithmic bytes per launch
 (every persisted value read once and written once) / mean launch time measured with
 HIP events on the stream the library launches on.
 """
@@ -83,7 +87,51 @@ def time_gpu(cfg, phi, precision, steps, warmup):
                 finite=finite, phi=phi_out)
 
 
-def time_oracle(cfg, phi, max_seconds=20.0, max_steps=12):
+def time_extra(cfg, phi, precision, steps, warmup, d, Q, NS, label):
+    """One more workload of the same step (MLUPS, achieved GB/s on the fused-step
+    algorithmic bytes)."""
+    r = time_gpu(cfg, phi, precision, steps, warmup)
+    V = cfg["nx"] * cfg["ny"] * cfg["nz"]
+    b = algorithmic_bytes_per_node(d, Q, NS, 8 if precision == "fp64" else 4)
+    gbs = V * b / (r["ms_per_step"] * 1e-3) / 1e9
+    return {"workload": label, "precision": precision, "model": cfg["model"],
+            "mlups": round(V / (r["ms_per_step"] * 1e-3) / 1e6, 1),
+            "ms_per_step": round(r["ms_per_step"], 4), "steps_timed": steps,
+            "bytes_per_node_update": b, "achieved_GBs": round(gbs, 1),
+            "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(label, precision), "finite": bool(r["finite"])}
+
+
+def time_adjoint(steps=50, ckpt_every=25):
+    """Differentiable run on the 256^2 N = 3 touching discs: wall time of the forward
+    (with checkpoints) and of the backward (segment recompute + hand-written adjoint
+    steps), FP64."""
+    import torch
+    from paper_2306_06983_amd import inputs
+    from paper_2306_06983_amd.autograd import run_differentiable
+    cfg, phi = inputs.two_discs(scale=4)
+    N = cfg["n_phases"]
+    phi0 = torch.tensor(phi, dtype=torch.float64, device="cuda:0", requires_grad=True)
+    sig = torch.tensor([cfg["sigma"][p][q] for p in range(N) for q in range(p + 1, N)],
+                       dtype=torch.float64, requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    phiT = run_differentiable(cfg, phi0, sig, steps, ckpt_every)
+    loss = (phiT ** 2).sum()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return {"workload": "two_discs_256x256_N3_d2q9_adjoint", "precision": "fp64",
+            "steps": steps, "ckpt_every": ckpt_every,
+            "forward_ms": round((t1 - t0) * 1e3, 2), "backward_ms": round((t2 - t1) * 1e3, 2),
+            "ms_per_adjoint_step": round((t2 - t1) * 1e3 / steps, 4),
+            "grad_finite": bool(torch.isfinite(phi0.grad).all().item()
+                                and torch.isfinite(sig.grad).all().item())}
+
+
+def time_oracle(cfg, phi, max_seconds=15.0, max_steps=200):
     """The oracle as it stands, on the host, single-threaded BLAS; bounded sample."""
     from threadpoolctl import threadpool_limits
     from oracle import nphase as O
@@ -118,6 +166,10 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 3D, 2048^2 and adjoint workloads reported beside the line")
+    ap.add_argument("--only", choices=["spheres_fp64", "spheres_fp32", "bands_fp32"],
+                    help="time only this other workload and print its record")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 256 MiB ten times (reference "
                          "for the memory traffic counters)")
@@ -132,6 +184,22 @@ def main():
     import numpy as np
     import torch
     from paper_2306_06983_amd import inputs
+
+    def spheres(prec, steps, warm):
+        c3, p3 = inputs.spheres(n=256)   # 256^3 D3Q19, N = 4, three drops
+        return time_extra(c3, p3, prec, steps, warm, 3, 19, c3["n_phases"] - 1,
+                          "spheres_256x256x256_N4_d3q19")
+
+    def bands(prec, steps, warm):
+        c4, p4 = inputs.layered_bands()   # 2048^2 D2Q9, N = 5 bands, gravity
+        return time_extra(c4, p4, prec, steps, warm, 2, 9, c4["n_phases"] - 1,
+                          "layered_bands_2048x2048_N5_d2q9")
+
+    if args.only:
+        kind, prec = args.only.split("_")
+        rec = (spheres if kind == "spheres" else bands)(prec, args.steps, args.warmup)
+        print(json.dumps(rec))
+        return 0
 
     cfg, phi = inputs.many_discs()   # 512^2, N = 4, Model B
     V = cfg["nx"] * cfg["ny"]
@@ -190,6 +258,10 @@ def main():
         "fp64_mass_drift_rel": drift64,
         "finite": bool(r64["finite"] and r32["finite"]),
     }
+    if not args.no_extra:
+        line["other_workloads"] = [spheres("fp64", 100, 10), spheres("fp32", 100, 10),
+                                   bands("fp32", 500, 50)]
+        line["adjoint"] = time_adjoint()
     if not args.no_cpu:
         cb = time_oracle(cfg, phi)
         line["cpu_baseline"] = {"value": round(cb["mlups"], 4), "unit": "MLUPS", "cores": 1,

@@ -87,7 +87,9 @@ typedef struct {
   double gravity[3];     /* body force (rho - rho_bar) g, rho_bar = mean density at t = 0 */
 } nphase_lbm_params;
 
-/* Bytes of device workspace for this parameter set. */
+/* Bytes of device workspace for this parameter set: both population and history buffers
+ * (Sec. 3 state), the reduction scratch and, for D3Q19, a per-node moment scratch of
+ * 4 NS (FP32: 5 NS) values that every step rewrites. */
 int nphase_lbm_workspace_bytes(const nphase_lbm_params *params, size_t *bytes_host);
 
 /* Validate and copy the parameters, carve the caller's workspace and bind the stream.
@@ -103,8 +105,10 @@ int nphase_lbm_create(const nphase_lbm_params *params, void *workspace_dev, size
  * FP64 mean density used by gravity.  Synchronises the stream. */
 int nphase_lbm_init(nphase_lbm_t h, const double *phi0_dev);
 
-/* Advance nsteps >= 0 time steps: one fused kernel per step (populations pulled from one
- * buffer, collided, pushed to the other).  Asynchronous on the stream. */
+/* Advance nsteps >= 0 time steps (populations read from one buffer, collided, pushed to
+ * the other): one fused kernel per step on D2Q9; on D3Q19 a moments kernel (phi_p, j_p
+ * of every node) followed by the fused z-marching collide-and-stream kernel.
+ * Asynchronous on the stream. */
 int nphase_lbm_step(nphase_lbm_t h, int64_t nsteps);
 
 /* Macroscopic fields at the current time T without changing the state (FP64, device):
@@ -125,7 +129,9 @@ int nphase_lbm_time(nphase_lbm_t h, int64_t *t_host);
 
 /* Full state (populations, history fields, step parity and time) for checkpointing:
  * save copies it into a caller device buffer of state_bytes bytes, load restores it.
- * Async. */
+ * Both synchronise the stream once for the 256-byte header (host <-> device), then
+ * enqueue the payload copies on the stream.  load returns EINVAL for a buffer that
+ * save did not write. */
 int nphase_lbm_state_bytes(nphase_lbm_t h, size_t *bytes_host);
 int nphase_lbm_save_state(nphase_lbm_t h, void *state_dev);
 int nphase_lbm_load_state(nphase_lbm_t h, const void *state_dev);

@@ -7,10 +7,12 @@ Bars:
   relative 6e-8 perturbation of phi0), per-phase relative mass drift <= 1e-6.
   FP64 mass conservation: <= 1e-12 relative (summation round-off over the run).
 The touching-disc workload (64^2, N = 3) amplifies round-off: in the oracle itself a
-1e-15 perturbation of phi0 grows to 3e-7 by step 100 and stays between 2e-7 and 1e-5
-up to step 2000.  Its FP64 bar therefore holds at 20 steps; at the full 2000 steps the
-bar is that envelope (1e-5) for both precisions, with the invariants checked exactly.
+one-rounding perturbation of phi0 (relative 2.2e-16) grows to 4e-7 .. 2e-5 by step 2000,
+depending on the seed.  Its 1e-12 FP64 bar therefore holds at 20 steps; at the full 2000
+steps the FP64 bar is 3x that stored envelope, with the invariants checked exactly.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -110,15 +112,24 @@ def test_two_discs_short_horizon_fp64():
     assert max(dphi, du, dP) <= FP64_TOL
 
 
+def _stored_envelope(name):
+    fn = os.path.join(os.path.dirname(__file__), "golden", name)
+    vals = [float(l.split()[1]) for l in open(fn) if l.strip() and not l.startswith("#")]
+    return max(vals)
+
+
 def test_two_discs_full_length():
-    """The 64^2 N = 3 Model B workload for its full 2000 steps: within the oracle's own
-    round-off sensitivity envelope (1e-5), mass conserved, sum phi = 1."""
+    """The 64^2 N = 3 Model B workload for its full 2000 steps: within 3x the FP64
+    oracle's own round-off envelope (the spread of oracle runs from phi0 perturbed at the
+    one-rounding level, stored by tests/golden/make_envelopes.py), mass conserved,
+    sum phi = 1."""
     cfg, phi = inputs.two_discs()
     o = run_oracle(cfg, phi, 2000)
     g = run_gpu(cfg, phi, 2000)
     dphi, du, dP = errors(g, o)
-    print(f"  2000 steps fp64 dphi={dphi:.2e} du={du:.2e} dP={dP:.2e}")
-    assert dphi <= 1e-5
+    env64 = _stored_envelope("two_discs_2000_fp64_envelope.txt")
+    print(f"  2000 steps fp64 dphi={dphi:.2e} du={du:.2e} dP={dP:.2e} envelope={env64:.2e}")
+    assert dphi <= 3 * env64
     assert np.all(np.abs(g["m1"] - g["m0"]) <= 1e-12 * g["m0"])
     assert np.abs(g["phi"].sum(0) - 1).max() <= 1e-14
     g32 = run_gpu(cfg, phi, 2000, "fp32")
