@@ -136,22 +136,34 @@ int nphase_lbm_state_bytes(nphase_lbm_t h, size_t *bytes_host);
 int nphase_lbm_save_state(nphase_lbm_t h, void *state_dev);
 int nphase_lbm_load_state(nphase_lbm_t h, const void *state_dev);
 
-/* ---- Discrete adjoint (FP64 handles, gravity = 0) --------------------------------------
- * The hand-written reverse of one time step.  With the state s^{t+1} = Step(s^t; sigma)
- * (the same step as nphase_lbm_step: Sec. 2.1 sources, Sec. 2.2 forces and mass flux,
- * Sec. 3 collisions, recovery and streaming) and a scalar loss L, the adjoint of a state
- * is dL/ds in the layout of a save_state buffer (256-byte header, then f, g, u^{t-1},
- * phi^{t-1}, m_phi^{t-1}; FP64; state_bytes bytes).  Guarded points of the forward (normals
- * below the guard, pair fractions of absent pairs) are differentiated as the constants the
+/* The current state as the FP64 populations it stands for, in the layout save_state writes
+ * for FP64 handles (256-byte header, then f, g, u^{t-1}, phi^{t-1}, m_phi^{t-1}; FP64):
+ * state64_bytes gives its size.  FP64 handles: identical to save_state.  FP32 handles:
+ * f_i = f~_i + w_i phi^{t-1} evaluated in FP64 (the deviation form of Sec. 3's populations),
+ * the other fields widened.  The adjoint entry points read and write this layout.
+ * Synchronises once for the header like save_state; the payload is written async.
+ * Such a buffer is not accepted by load_state of an FP32 handle. */
+int nphase_lbm_state64_bytes(nphase_lbm_t h, size_t *bytes_host);
+int nphase_lbm_save_state64(nphase_lbm_t h, void *state64_dev);
+
+/* ---- Discrete adjoint (gravity = 0) -------------------------------------------------------
+ * The hand-written reverse of one time step, in FP64 arithmetic.  With the state
+ * s^{t+1} = Step(s^t; sigma) (the same step as nphase_lbm_step: Sec. 2.1 sources, Sec. 2.2
+ * forces and mass flux, Sec. 3 collisions, recovery and streaming) and a scalar loss L, the
+ * adjoint of a state is dL/ds in the layout of a save_state64 buffer (256-byte header, then
+ * f, g, u^{t-1}, phi^{t-1}, m_phi^{t-1}; FP64; state64_bytes bytes), and the forward states
+ * it is given are save_state64 buffers.  For FP32 handles this is the adjoint of the FP64
+ * step evaluated along the FP32 trajectory.  Guarded points of the forward (normals below
+ * the guard, pair fractions of absent pairs) are differentiated as the constants the
  * forward returns there.  The gravity reference density is treated as fixed, so these
- * entry points return NPHASE_ENOTSUP for FP32 handles or non-zero gravity.
+ * entry points return NPHASE_ENOTSUP for non-zero gravity.
  *
  * adjoint_workspace_bytes: device scratch for one adjoint step (caller-owned).
  * adjoint_seed:  adj_state = dL/ds^T for L depending on the phase fields phi(T) [N][V]
  *                through dL_dphi_dev [N][nz][ny][nx] (phi_N = 1 - sum when N-1 sets are
  *                evolved).  Async.
  * adjoint_step:  adj_out = (dStep/ds^t)^T adj_in, given the forward state s^t (a
- *                save_state buffer); adds (dStep/dsigma_pq)^T adj_in to per-block partials in
+ *                save_state64 buffer); adds (dStep/dsigma_pq)^T adj_in to per-block partials in
  *                the workspace.  adj_in and adj_out must be different buffers.  Async.
  * adjoint_sigma: dL/dsigma_pq summed over the steps since the last reset, written to an
  *                N x N row-major host matrix with stride NPHASE_MAX_N (both [p][q] and [q][p]

@@ -1,10 +1,13 @@
 """Differentiable run of the N-phase LBM: a torch.autograd.Function over the C ABI.
 
-    phiT = run_differentiable(cfg, phi0, sigma_pairs, steps, ckpt_every=50)
+    phiT = run_differentiable(cfg, phi0, sigma_pairs, steps, ckpt_every=50, precision="fp64")
 
 forward: init from phi0 [N, *grid] (FP64), run `steps` fused steps on the GPU with the
 pair tensions sigma_pairs (p < q, lexicographic), keep a checkpoint of the state every
-`ckpt_every` steps, return the N phase fields at the end.
+`ckpt_every` steps, return the N phase fields at the end.  With precision "fp32" the
+forward runs the FP32 deviation-storage form and the backward applies the (FP64) adjoint
+step along that FP32 trajectory: each recomputed state is exported as the FP64
+populations it stands for.
 backward: seed the state adjoint from dL/dphiT, then for each checkpoint segment from the
 last: restore the checkpoint, recompute the segment's states with the forward kernel, and
 run the hand-written adjoint step backwards through them; finally map the adjoint of the
@@ -19,9 +22,9 @@ from . import inputs
 
 class NPhaseRun(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, phi0, sigma_pairs, cfg, steps, ckpt_every):
+    def forward(ctx, phi0, sigma_pairs, cfg, steps, ckpt_every, precision):
         cfg_s = inputs.with_sigma_pairs(cfg, sigma_pairs.detach().cpu().numpy())
-        sim = B.Sim(cfg_s, "fp64", device=str(phi0.device))
+        sim = B.Sim(cfg_s, precision, device=str(phi0.device))
         sim.init(phi0.detach())
         ckpts = []
         t = 0
@@ -49,7 +52,7 @@ class NPhaseRun(torch.autograd.Function):
             sim.load_state(buf)
             states = []
             for _ in range(n):
-                states.append(sim.save_state())
+                states.append(sim.save_state64())
                 sim.step(1)
             for st in reversed(states):
                 sim.adjoint_step(st, lam, lam2, ws)
@@ -59,10 +62,11 @@ class NPhaseRun(torch.autograd.Function):
         N = ctx.N
         pairs = [dsig[p, q] for p in range(N) for q in range(p + 1, N)]
         dpairs = torch.tensor(pairs, dtype=torch.float64)
-        return dphi0, dpairs, None, None, None
+        return dphi0, dpairs, None, None, None, None
 
 
-def run_differentiable(cfg, phi0, sigma_pairs, steps, ckpt_every=50):
+def run_differentiable(cfg, phi0, sigma_pairs, steps, ckpt_every=50, precision="fp64"):
     """Phase fields [N, *grid] after `steps` steps, differentiable w.r.t. phi0 and the pair
-    tensions (FP64 on the current CUDA device; gravity must be zero)."""
-    return NPhaseRun.apply(phi0, sigma_pairs, cfg, int(steps), int(ckpt_every))
+    tensions (on phi0's CUDA device; gravity must be zero).  precision "fp64" or "fp32"
+    (the forward's storage and arithmetic; the adjoint steps are FP64)."""
+    return NPhaseRun.apply(phi0, sigma_pairs, cfg, int(steps), int(ckpt_every), precision)

@@ -75,6 +75,8 @@ def load():
         "nphase_lbm_state_bytes": [vp, ctypes.POINTER(sz)],
         "nphase_lbm_save_state": [vp, vp],
         "nphase_lbm_load_state": [vp, vp],
+        "nphase_lbm_state64_bytes": [vp, ctypes.POINTER(sz)],
+        "nphase_lbm_save_state64": [vp, vp],
         "nphase_lbm_destroy": [vp],
         "nphase_lbm_adjoint_workspace_bytes": [vp, ctypes.POINTER(sz)],
         "nphase_lbm_adjoint_seed": [vp, vp, vp],
@@ -223,7 +225,20 @@ class Sim:
         self._rc(self.lib.nphase_lbm_load_state(self.h, ctypes.c_void_p(buf.data_ptr())))
         return self
 
-    # ---- discrete adjoint (FP64 handles) -------------------------------------------------
+    def state64_bytes(self):
+        n = ctypes.c_size_t()
+        self._rc(self.lib.nphase_lbm_state64_bytes(self.h, ctypes.byref(n)))
+        return n.value
+
+    def save_state64(self, buf=None):
+        """The state as FP64 populations (the layout the adjoint reads)."""
+        t = self.torch
+        if buf is None:
+            buf = t.empty(self.state64_bytes(), dtype=t.uint8, device=self.device)
+        self._rc(self.lib.nphase_lbm_save_state64(self.h, ctypes.c_void_p(buf.data_ptr())))
+        return buf
+
+    # ---- discrete adjoint (FP64 arithmetic; state buffers in the save_state64 layout) -----
     def adjoint_workspace(self):
         n = ctypes.c_size_t()
         self._rc(self.lib.nphase_lbm_adjoint_workspace_bytes(self.h, ctypes.byref(n)))
@@ -234,7 +249,7 @@ class Sim:
         t = self.torch
         x = dL_dphi.to(device=self.device, dtype=t.float64).contiguous()
         if buf is None:
-            buf = t.zeros(self.state_bytes(), dtype=t.uint8, device=self.device)
+            buf = t.zeros(self.state64_bytes(), dtype=t.uint8, device=self.device)
         self._rc(self.lib.nphase_lbm_adjoint_seed(self.h, ctypes.c_void_p(x.data_ptr()),
                                                   ctypes.c_void_p(buf.data_ptr())))
         return buf

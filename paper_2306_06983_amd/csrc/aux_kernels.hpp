@@ -44,6 +44,37 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// The state as the FP64 populations it stands for: FP64 copies it; FP32 widens it and adds
+// the rest weights of phi^{t-1} back, f_i = f~_i + w_i phi^{t-1}, evaluated in FP64.
+template <typename T, int LAT>
+__global__ void __launch_bounds__(256)
+    state_to64_kernel(const T* __restrict__ f, const T* __restrict__ g, const T* __restrict__ u,
+                      const T* __restrict__ pm, const T* __restrict__ mm,
+                      double* __restrict__ f64, double* __restrict__ g64, double* __restrict__ u64,
+                      double* __restrict__ pm64, double* __restrict__ mm64, int NS, long long V) {
+  using L = Lattice<LAT>;
+  constexpr int Q = L::Q, D = L::D;
+  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= V) return;
+  for (int p = 0; p < NS; ++p) {
+    const double ph = (double)pm[(long long)p * V + x];
+    pm64[(long long)p * V + x] = ph;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      double v = (double)f[(long long)(p * Q + i) * V + x];
+      if (sizeof(T) == 4) v += L::w(i) * ph;
+      f64[(long long)(p * Q + i) * V + x] = v;
+    }
+  }
+#pragma unroll
+  for (int i = 1; i < Q; ++i) g64[(long long)(i - 1) * V + x] = (double)g[(long long)(i - 1) * V + x];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    u64[(long long)d * V + x] = (double)u[(long long)d * V + x];
+    mm64[(long long)d * V + x] = (double)mm[(long long)d * V + x];
+  }
+}
+
 // Per-block FP64 partial sums of every phase: phi_p = sum_i f_{i,p} (FP64: plain sum;
 // FP32: phi^{-1} + sum_i f~_i evaluated exactly in FP64), phi_N = 1 - sum when N-1 sets
 // are evolved.  partial[p * RED_BLOCKS + block].

@@ -164,10 +164,12 @@ void fill_args(nphase_lbm_t h, StepArgs<T>* out) {
       a.rho[i] = (T)p.rho[i];
       // mu_p = rho_p (tau_g,p - 1/2) c_s^2  (Sec. 3)
       a.mu[i] = (T)(p.rho[i] * (p.tau_g[i] - 0.5) * CS2);
-      for (int j = 0; j < h->N; ++j) {
+    }
+    for (int i = 0, k = 0; i < h->N; ++i) {
+      for (int j = i + 1; j < h->N; ++j, ++k) {
         const double s = p.sigma[i * NPHASE_MAX_N + j];
-        a.beta2[i * MAXN + j] = (T)(2.0 * 3.0 * s / p.eps);   // 2 beta_pq, beta = 3 sigma/eps
-        a.kappa[i * MAXN + j] = (T)(-0.75 * p.eps * s);       // k_pq = -3 eps sigma / 4
+        a.beta2[k] = (T)(2.0 * 3.0 * s / p.eps);   // 2 beta_pq, beta = 3 sigma / eps
+        a.kappa[k] = (T)(-0.75 * p.eps * s);       // k_pq = -3 eps sigma / 4
       }
     }
     a.mob = (T)p.mobility;
@@ -423,6 +425,17 @@ struct StateHeader {
   int64_t magic;
 };
 
+// 256-byte header of a state buffer (time, gravity reference density, magic)
+static int put_header(nphase_lbm_t h, void* state_dev) {
+  static thread_local StateHeader hdr;
+  hdr.t = h->t;
+  hdr.rho_bar = h->rho_bar;
+  hdr.magic = 0x4e5048415345;
+  HIPCHK(hipMemcpyAsync(state_dev, &hdr, sizeof(hdr), hipMemcpyHostToDevice, h->stream), "save header");
+  HIPCHK(hipStreamSynchronize(h->stream), "save header sync");
+  return NPHASE_OK;
+}
+
 int nphase_lbm_save_state(nphase_lbm_t h, void* state_dev) {
   int rc = check_handle(h);
   if (rc) return rc;
@@ -430,14 +443,9 @@ int nphase_lbm_save_state(nphase_lbm_t h, void* state_dev) {
   if (!h->inited) { h->err = "save before init"; return NPHASE_ESTATE; }
   size_t parts[5];
   state_payload(h, parts);
-  static thread_local StateHeader hdr;
-  hdr.t = h->t;
-  hdr.rho_bar = h->rho_bar;
-  hdr.magic = 0x4e5048415345;
-  char* q = (char*)state_dev;
-  HIPCHK(hipMemcpyAsync(q, &hdr, sizeof(hdr), hipMemcpyHostToDevice, h->stream), "save header");
-  HIPCHK(hipStreamSynchronize(h->stream), "save header sync");
-  q += ALIGN;
+  rc = put_header(h, state_dev);
+  if (rc) return rc;
+  char* q = (char*)state_dev + ALIGN;
   const void* src[5] = {h->f[h->cur], h->g[h->cur], h->u[h->cur], h->pm[h->cur], h->mm};
   for (int k = 0; k < 5; ++k) {
     HIPCHK(hipMemcpyAsync(q, src[k], parts[k], hipMemcpyDeviceToDevice, h->stream), "save copy");
@@ -585,7 +593,6 @@ hipError_t adj_launch(nphase_lbm_t h, int which, const AdjArgs& a) {
 int adj_check(nphase_lbm_t h) {
   int rc = check_handle(h);
   if (rc) return rc;
-  if (h->prec != NPHASE_FP64) { h->err = "the adjoint is built for FP64 handles"; return NPHASE_ENOTSUP; }
   if (h->prm.gravity[0] != 0.0 || h->prm.gravity[1] != 0.0 || h->prm.gravity[2] != 0.0) {
     h->err = "the adjoint treats the gravity reference density as fixed: needs gravity = 0";
     return NPHASE_ENOTSUP;
@@ -667,6 +674,38 @@ int nphase_lbm_adjoint_sigma(nphase_lbm_t h, void* adj_ws_dev, double* dL_dsigma
     hipLaunchKernelGGL(zero_double_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->stream, part, n);
     HIPCHK(hipGetLastError(), "sigma reset");
   }
+  return NPHASE_OK;
+}
+
+int nphase_lbm_state64_bytes(nphase_lbm_t h, size_t* bytes_host) {
+  if (!h || !bytes_host) return NPHASE_EINVAL;
+  size_t parts[5];
+  *bytes_host = ALIGN + state_payload(h, parts) / h->tsize * sizeof(double);
+  return NPHASE_OK;
+}
+
+int nphase_lbm_save_state64(nphase_lbm_t h, void* state_dev) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (h->prec == NPHASE_FP64) return nphase_lbm_save_state(h, state_dev);
+  if (!state_dev) { h->err = "state buffer is NULL"; return NPHASE_EINVAL; }
+  if (!h->inited) { h->err = "save before init"; return NPHASE_ESTATE; }
+  rc = put_header(h, state_dev);
+  if (rc) return rc;
+  const StatePtrs o = state_ptrs(h, state_dev);
+  const int c = h->cur;
+  const unsigned nb = (unsigned)((h->V + 255) / 256);
+  if (h->lat == NPHASE_D2Q9)
+    hipLaunchKernelGGL((state_to64_kernel<float, LAT_D2Q9>), dim3(nb), dim3(256), 0, h->stream,
+                       (const float*)h->f[c], (const float*)h->g[c], (const float*)h->u[c],
+                       (const float*)h->pm[c], (const float*)h->mm, o.f, o.g, o.u, o.pm, o.mm,
+                       h->NS, h->V);
+  else
+    hipLaunchKernelGGL((state_to64_kernel<float, LAT_D3Q19>), dim3(nb), dim3(256), 0, h->stream,
+                       (const float*)h->f[c], (const float*)h->g[c], (const float*)h->u[c],
+                       (const float*)h->pm[c], (const float*)h->mm, o.f, o.g, o.u, o.pm, o.mm,
+                       h->NS, h->V);
+  HIPCHK(hipGetLastError(), "save state64");
   return NPHASE_OK;
 }
 

@@ -348,9 +348,8 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 2 : 1) nphase_step3
         s2_node(rown, zs2, true, G, Lp, R, phc, mpn);
         store_w(iown, zs2, col_own + plane * wrap(zs2, nz), mpn);
         // chemical potentials and the potential-form surface tension (Sec. 2.2)
-        T gp[N];
-#pragma unroll
-        for (int p = 0; p < N; ++p) gp[p] = gprime(phc[p]);
+        T mu_phi[N];
+        chemical_potentials<T, N>(a, phc, Lp, mu_phi);
 #pragma unroll
         for (int d = 0; d < D; ++d) {
           Fsn[d] = T(0);
@@ -361,17 +360,9 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 2 : 1) nphase_step3
 #pragma unroll
           for (int d = 0; d < D; ++d) grn[d] += a.rho[p] * G[p][d];
 #pragma unroll
-        for (int p = 0; p < N; ++p) {
-          T mu_p = T(0);
+        for (int p = 0; p < N; ++p)
 #pragma unroll
-          for (int q = 0; q < N; ++q)
-            if (q != p) mu_p += a.beta2[p * MAXN + q] * (gp[p] - gprime(phc[p] + phc[q]));
-#pragma unroll
-          for (int q = 0; q < N; ++q)
-            if (q != p) mu_p -= a.kappa[p * MAXN + q] * Lp[q];
-#pragma unroll
-          for (int d = 0; d < D; ++d) Fsn[d] += mu_p * G[p][d];
-        }
+          for (int d = 0; d < D; ++d) Fsn[d] += mu_phi[p] * G[p][d];
 #pragma unroll
         for (int p = 0; p < NS; ++p)
 #pragma unroll

@@ -1,6 +1,6 @@
 // Fused time step of the consistent and conservative N-phase LBM (one kernel per step).
 //
-// Per workgroup: one tile of TX x TY (x TZ) nodes, one node per thread (256 threads).
+// Per workgroup: one tile of TX x TY (x TZ) nodes, one node per thread.
 //   stage 1  region = tile + 2-node halo: phi_p = sum_i f_{i,p} (Sec. 3 macroscopic
 //            recovery) for the evolved sets, phi_N = 1 - sum (Sec. 4 intro), and for
 //            Model B the pairwise fractions phi_pq = phi_p/(phi_p + phi_q) (Sec. 2.1);
@@ -66,8 +66,10 @@ struct StepArgs {
   int model_a_n;
   T rho[MAXN];
   T mu[MAXN];
-  T beta2[MAXN * MAXN];   // 2 beta_pq = 6 sigma_pq / eps
-  T kappa[MAXN * MAXN];   // k_pq = -3 eps sigma_pq / 4
+  // per unordered pair p < q (lexicographic): 2 beta_pq = 6 sigma_pq / eps and
+  // k_pq = -3 eps sigma_pq / 4 (both symmetric in p, q)
+  T beta2[MAXN * (MAXN - 1) / 2];
+  T kappa[MAXN * (MAXN - 1) / 2];
   T mob;                  // M
   T s1;                   // 1 / tau_f
   T four_over_eps;        // 4 / eps
@@ -78,13 +80,15 @@ struct StepArgs {
 template <int LAT>
 struct TileShape;
 template <>
-struct TileShape<LAT_D2Q9> {
+struct TileShape<LAT_D2Q9> {   // one node per thread: the workgroup has TX * TY threads
   static constexpr int TX = 32, TY = 8, TZ = 1;
+  static constexpr int NT = TX * TY * TZ;
 };
 template <>
 struct TileShape<LAT_D3Q19> {   // used by the tile kernel only if instantiated for D3Q19;
   static constexpr int TX = 8, TY = 8, TZ = 4;   // the library runs D3Q19 on the
-};                                                 // z-marching kernel (step3d_kernel.hpp)
+  static constexpr int NT = TX * TY * TZ;        // z-marching kernel (step3d_kernel.hpp)
+};
 
 __device__ __forceinline__ int wrap(int v, int n) {
   int r = v % n;
@@ -137,6 +141,30 @@ __device__ __forceinline__ T gprime(T p) {  // g(phi) = phi^2 (1 - phi)^2
   return T(2) * p * (T(1) - p) * (T(1) - T(2) * p);
 }
 
+// Chemical potentials mu_phi_p = sum_{q != p} 2 beta_pq [g'(phi_p) - g'(phi_p + phi_q)]
+//                                - sum_{q != p} k_pq lap phi_q   (Sec. 2.2), pair by pair.
+template <typename T, int N, typename A>
+__device__ __forceinline__ void chemical_potentials(const A& a, const T* ph, const T* lap,
+                                                    T* mu) {
+  T gp[N];
+#pragma unroll
+  for (int p = 0; p < N; ++p) {
+    gp[p] = gprime(ph[p]);
+    mu[p] = T(0);
+  }
+  int k = 0;
+#pragma unroll
+  for (int p = 0; p < N; ++p) {
+#pragma unroll
+    for (int q = p + 1; q < N; ++q, ++k) {
+      const T gpq = gprime(ph[p] + ph[q]);
+      const T b = a.beta2[k], kk = a.kappa[k];
+      mu[p] += b * (gp[p] - gpq) - kk * lap[q];
+      mu[q] += b * (gp[q] - gpq) - kk * lap[p];
+    }
+  }
+}
+
 // Model B pairwise fraction phi_pq = phi_p / (phi_p + phi_q), 1/2 where both vanish
 template <typename T>
 __device__ __forceinline__ T pair_fraction(T pp, T pq) {
@@ -145,7 +173,7 @@ __device__ __forceinline__ T pair_fraction(T pp, T pq) {
 }
 
 template <typename T, int LAT, int N, bool SA, int MODEL, int MODE>
-__global__ void __launch_bounds__(NTHREADS) nphase_step_kernel(const StepArgs<T> a) {
+__global__ void __launch_bounds__(TileShape<LAT>::NT) nphase_step_kernel(const StepArgs<T> a) {
   using L = Lattice<LAT>;
   constexpr int D = L::D;
   constexpr int Q = L::Q;
@@ -154,7 +182,7 @@ __global__ void __launch_bounds__(NTHREADS) nphase_step_kernel(const StepArgs<T>
   constexpr bool DEV = sizeof(T) == 4;   // FP32 deviation storage
   using TS = TileShape<LAT>;
   constexpr int TX = TS::TX, TY = TS::TY, TZ = (D == 3) ? TS::TZ : 1;
-  static_assert(TX * TY * TZ == NTHREADS, "one node per thread");
+  constexpr int NTH = TS::NT;   // threads per workgroup, one node each
   constexpr int RX = TX + 4, RY = TY + 4, RZ = (D == 3) ? TZ + 4 : 1;
   constexpr int NR = RX * RY * RZ;
   constexpr int IX = TX + 2, IY = TY + 2, IZ = (D == 3) ? TZ + 2 : 1;
@@ -278,8 +306,8 @@ __global__ void __launch_bounds__(NTHREADS) nphase_step_kernel(const StepArgs<T>
   };
   stage1(r_own, g_own, true);
   {
-    constexpr int NRING = NR - NTHREADS;
-    for (int k = t; k < NRING; k += NTHREADS) {
+    constexpr int NRING = NR - NTH;
+    for (int k = t; k < NRING; k += NTH) {
       int rx, ry, rz;
       ring_coord<2, RX, RY, RZ>(k, rx, ry, rz);
       stage1(rx + RX * (ry + RY * rz), region_gidx(rx, ry, rz), false);
@@ -429,8 +457,8 @@ __global__ void __launch_bounds__(NTHREADS) nphase_step_kernel(const StepArgs<T>
     }
   };
   {
-    constexpr int NIRING = NI - NTHREADS;
-    for (int k = t; k < NIRING; k += NTHREADS) {
+    constexpr int NIRING = NI - NTH;
+    for (int k = t; k < NIRING; k += NTH) {
       int ix, iy, iz;
       ring_coord<1, IX, IY, IZ>(k, ix, iy, iz);
       const int rz = (D == 3) ? iz + 1 : 0;
@@ -501,21 +529,12 @@ __global__ void __launch_bounds__(NTHREADS) nphase_step_kernel(const StepArgs<T>
 #pragma unroll
     for (int d = 0; d < D; ++d) grho[d] += a.rho[p] * G[p][d];
   {
-    T gp[N];
+    T mu_phi[N];
+    chemical_potentials<T, N>(a, phi_own, Lp, mu_phi);
 #pragma unroll
-    for (int p = 0; p < N; ++p) gp[p] = gprime(phi_own[p]);
+    for (int p = 0; p < N; ++p)
 #pragma unroll
-    for (int p = 0; p < N; ++p) {
-      T m = T(0);
-#pragma unroll
-      for (int q = 0; q < N; ++q)
-        if (q != p) m += a.beta2[p * MAXN + q] * (gp[p] - gprime(phi_own[p] + phi_own[q]));
-#pragma unroll
-      for (int q = 0; q < N; ++q)
-        if (q != p) m -= a.kappa[p * MAXN + q] * Lp[q];
-#pragma unroll
-      for (int d = 0; d < D; ++d) F[d] += m * G[p][d];
-    }
+      for (int d = 0; d < D; ++d) F[d] += mu_phi[p] * G[p][d];
   }
 #pragma unroll
   for (int d = 0; d < D; ++d) F[d] = F[d] + (rho - a.rho_bar) * a.grav[d] + Fc[d];
