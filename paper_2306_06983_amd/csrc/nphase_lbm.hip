@@ -282,7 +282,10 @@ int nphase_lbm_create(const nphase_lbm_params* params, void* workspace_dev, size
   if (h->lat == NPHASE_D2Q9) {
     TX = TileShape<LAT_D2Q9>::TX; TY = TileShape<LAT_D2Q9>::TY; TZ = 1;
   } else {
-    TX = Z3_TX; TY = Z3_TY; TZ = Z3_ZR;   // z-marching: columns x planes per workgroup
+    // z-marching: columns x planes per workgroup
+    TX = h->prec == NPHASE_FP64 ? Z3Tile<double>::TX : Z3Tile<float>::TX;
+    TY = h->prec == NPHASE_FP64 ? Z3Tile<double>::TY : Z3Tile<float>::TY;
+    TZ = Z3_ZR;
   }
   h->ntx = (params->nx + TX - 1) / TX;
   h->nty = (params->ny + TY - 1) / TY;

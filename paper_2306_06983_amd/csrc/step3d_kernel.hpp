@@ -7,8 +7,8 @@
 // the populations only through these moments (the collisions are in closed form), so the
 // halo of the stencils reads 1 value per phase and node instead of Q.
 //
-// nphase_step3d_kernel: a workgroup of 256 threads owns a 16 x 16 column tile (one thread
-// per column) and a run of ZR planes in z.  It marches through the run with a three-stage
+// nphase_step3d_kernel: a workgroup of 256 threads owns a TX x TY column tile (one thread
+// per column; 64 x 4 in FP64, 32 x 8 in FP32) and a run of ZR planes in z.  It marches through the run with a three-stage
 // pipeline, one plane per stage and iteration:
 //   S1 plane z+2   phi (and Model B pair fractions) on the tile plus a 2-node ring in x,y,
 //                  from the moments, into a ring of LDS planes;
@@ -18,9 +18,10 @@
 //   S3 plane z     correction force from that tensor, forces, u, P, the closed-form
 //                  moment-space collisions and push streaming (Sec. 2.2, Sec. 3).
 // The own-node results of S2 are kept in registers for the S3 of the next iteration.  The
-// halo is recomputed only in x and y (1.56x the phi loads for the 20 x 20 region plane,
-// and 1.27x the S2 work for the 18 x 18 inner plane); in z every plane is computed once
-// per run plus 4 pipeline-fill planes.  The arithmetic is the same as the tile kernel's.
+// halo is recomputed only in x and y (FP64: 2.1x the phi loads for the 68 x 8 region
+// plane and 1.55x the S2 work for the 66 x 6 inner plane; FP32: 1.69x and 1.33x); in z
+// every plane is computed once per run plus 4 pipeline-fill planes.  The arithmetic is the
+// same as the tile kernel's.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -30,8 +31,15 @@
 
 namespace nphase {
 
-constexpr int Z3_TX = 16, Z3_TY = 16;   // columns per workgroup
-constexpr int Z3_ZR = 32;               // planes per workgroup run
+// Column tile of a workgroup (TX * TY = 256 threads) and planes per run.  Rows of 64 (FP64)
+// or 32 (FP32) nodes keep the x-shifted pushes of a wave on few partial cache lines; FP32
+// uses the narrower tile so that the Model B pair fractions still fit its LDS budget.
+template <typename T>
+struct Z3Tile {
+  static constexpr int TX = sizeof(T) == 8 ? 64 : 32;
+  static constexpr int TY = 256 / TX;
+};
+constexpr int Z3_ZR = 32;   // planes per workgroup run
 
 // Moments of one node, layout mo[NM][V]: [p] phi_p, [NS + p D + d] j_{p,d}, and for FP32
 // [NS + NS D + p] the two-sum residual (phi^{t-1} + sum f~) - phi of the rounded phi.
@@ -87,7 +95,7 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 2 : 1) nphase_step3
   constexpr int NS = SA ? N : N - 1;
   constexpr int NP = N * (N - 1) / 2;
   constexpr bool DEV = sizeof(T) == 4;
-  constexpr int TX = Z3_TX, TY = Z3_TY, ZR = Z3_ZR;
+  constexpr int TX = Z3Tile<T>::TX, TY = Z3Tile<T>::TY, ZR = Z3_ZR;
   constexpr int RX = TX + 4, RY = TY + 4, RP = RX * RY;   // region plane (2-node ring)
   constexpr int IX = TX + 2, IY = TY + 2, IP = IX * IY;   // inner plane (1-node ring)
   constexpr int PHR = DEV ? 5 : 3;                        // phi ring depth
