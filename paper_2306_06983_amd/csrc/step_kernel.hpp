@@ -249,18 +249,24 @@ __global__ void __launch_bounds__(TileShape<LAT>::NT) nphase_step_kernel(const S
   T j_own[NS][D];
   T pm_own[NS];
   T res_own[NS];   // FP32: exact rounding residual of phi = phi^{t-1} + sum f~ (own node)
-  auto stage1 = [&](int r, long long gi, bool own) {
+  // populations (and FP32 phi^{t-1}) of the evolved sets at one node
+  auto load_node = [&](long long gi, T (&v)[NS][Q], T (&pmv)[NS]) {
+#pragma unroll
+    for (int p = 0; p < NS; ++p) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) v[p][i] = LD(a.f_src, p * Q + i, (unsigned)gi);
+      if constexpr (DEV) pmv[p] = LD(a.pm_src, p, (unsigned)gi);
+    }
+  };
+  auto stage1 = [&](int r, const T (&v)[NS][Q], const T (&pmv)[NS], bool own) {
     T ph[N];
 #pragma unroll
     for (int p = 0; p < NS; ++p) {
-      T v[Q];
+      T s = v[p][0];
 #pragma unroll
-      for (int i = 0; i < Q; ++i) v[i] = LD(a.f_src, p * Q + i, (unsigned)gi);
-      T s = v[0];
-#pragma unroll
-      for (int i = 1; i < Q; ++i) s += v[i];
+      for (int i = 1; i < Q; ++i) s += v[p][i];
       if constexpr (DEV) {
-        const T pm = LD(a.pm_src, p, (unsigned)gi);
+        const T pm = pmv[p];
         const T sum = pm + s;
         if (own) {
           // two-sum: (pm + s) - sum exactly; it is re-injected into the rest deviation
@@ -279,8 +285,8 @@ __global__ void __launch_bounds__(TileShape<LAT>::NT) nphase_step_kernel(const S
           T jj = T(0);
 #pragma unroll
           for (int i = 1; i < Q; ++i) {
-            if (L::c(i, d) == 1) jj += v[i];
-            if (L::c(i, d) == -1) jj -= v[i];
+            if (L::c(i, d) == 1) jj += v[p][i];
+            if (L::c(i, d) == -1) jj -= v[p][i];
           }
           j_own[p][d] = jj;
         }
@@ -304,13 +310,33 @@ __global__ void __launch_bounds__(TileShape<LAT>::NT) nphase_step_kernel(const S
       }
     }
   };
-  stage1(r_own, g_own, true);
   {
     constexpr int NRING = NR - NTH;
-    for (int k = t; k < NRING; k += NTH) {
-      int rx, ry, rz;
-      ring_coord<2, RX, RY, RZ>(k, rx, ry, rz);
-      stage1(rx + RX * (ry + RY * rz), region_gidx(rx, ry, rz), false);
+    T vo[NS][Q], pmo[NS];
+    load_node(g_own, vo, pmo);
+    if constexpr (DEV && NRING <= NTH) {
+      // FP32: the ring node's loads (at most one per thread) are issued before the own
+      // node is reduced, so that both are in flight together
+      const bool ring = t < NRING;
+      T vr[NS][Q], pmr[NS];
+      int rr = 0;
+      if (ring) {
+        int rx, ry, rz;
+        ring_coord<2, RX, RY, RZ>(t, rx, ry, rz);
+        rr = rx + RX * (ry + RY * rz);
+        load_node(region_gidx(rx, ry, rz), vr, pmr);
+      }
+      stage1(r_own, vo, pmo, true);
+      if (ring) stage1(rr, vr, pmr, false);
+    } else {
+      stage1(r_own, vo, pmo, true);
+      for (int k = t; k < NRING; k += NTH) {
+        int rx, ry, rz;
+        ring_coord<2, RX, RY, RZ>(k, rx, ry, rz);
+        T vr[NS][Q], pmr[NS];
+        load_node(region_gidx(rx, ry, rz), vr, pmr);
+        stage1(rx + RX * (ry + RY * rz), vr, pmr, false);
+      }
     }
   }
   __syncthreads();
