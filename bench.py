@@ -169,6 +169,27 @@ def time_oracle(cfg, phi, max_seconds=15.0, max_steps=200):
     return dict(mlups=V * n / dt / 1e6, steps=n, seconds=dt)
 
 
+def copy_rate(nbytes, reps=50):
+    """GB/s of a plain device-to-device copy that reads and writes nbytes (torch's copy
+    kernel): the practical streaming rate of this device at that size."""
+    import torch
+    src = torch.ones(max(nbytes // 8, 1), dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def copy_calibration(nbytes=256 << 20, reps=10):
     """A plain copy kernel of known size: reads and writes nbytes per launch."""
     import torch
@@ -243,6 +264,8 @@ def main():
     ach32 = V * b32 / (r32["ms_per_step"] * 1e-3) / 1e9
     workload = "many_discs_512x512_N4_d2q9"
     tr = measured_traffic(workload, "fp64")
+    # a copy moving the same bytes per launch (half read, half written)
+    cr64 = copy_rate(V * b64 // 2)
 
     # FP32 accuracy at the end of the timed run against the FP64 path (same steps)
     dphi32 = float((r32["phi"] - r64["phi"]).abs().max().item())
@@ -268,6 +291,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(ach64, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(ach64 / HBM_PEAK_GBS, 4),
                      "traffic": tr, "bytes_per_node_update": b64,
+                     "copy_GBs_same_bytes": round(cr64, 1),
+                     "frac_of_copy": round(ach64 / cr64, 4),
                      "note": "state (about 180 MB with both buffers) is smaller than the "
                              "256 MB Infinity Cache"},
         "fp32": {"value": round(mlups(r32), 1), "ms_per_step": r32["ms_per_step"],

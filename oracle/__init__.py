@@ -12,7 +12,10 @@ Modules
 lattice  D2Q9 (the paper's natural moment matrix, Sec. 4 intro) and D3Q19 (raw-moment
          basis of the same construction; the paper only uses D2Q9).
 nphase   parameters, initial state, one time step (whole-grid NumPy arrays, literal
-         moment-space collisions M^-1 S M), macroscopic fields and per-phase mass.
-fd       central finite differences of a phase-field misfit through the oracle, used to
-         check the adjoint.
+         moment-space collisions M^-1 S M), macroscopic fields and per-phase mass.  The
+         adjoint tests take central finite differences of losses through it.
+nphase_loops
+         the same step written a second time, node by node with explicit periodic
+         neighbour coordinates and per-node moment-matrix products (tiny grids only);
+         it cross-checks the vectorised module.
 """
