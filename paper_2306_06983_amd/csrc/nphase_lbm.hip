@@ -67,10 +67,14 @@ Layout layout_of(const nphase_lbm_params& p) {
   const size_t V = (size_t)p.nx * (size_t)p.ny * (size_t)p.nz;
   const size_t ts = p.precision == NPHASE_FP64 ? 8 : 4;
   Layout L;
-  L.f = align_up((size_t)NS * Q * V * ts);
+  // D3Q19 keeps the phase field in moment form (phi, A, D per set; FP32 also the residual),
+  // whose phi slot is the next step's phi^{t-1}: no separate phi^{t-1} buffers
+  const bool mr = p.lattice == NPHASE_D3Q19;
+  const size_t nmr = ts == 4 ? MR<float>::N : MR<double>::N;
+  L.f = align_up((size_t)NS * (mr ? nmr : (size_t)Q) * V * ts);
   L.g = align_up((size_t)(Q - 1) * V * ts);
   L.u = align_up((size_t)D * V * ts);
-  L.pm = align_up((size_t)NS * V * ts);
+  L.pm = mr ? 0 : align_up((size_t)NS * V * ts);
   L.mm = align_up((size_t)D * V * ts);
   // D3Q19: per-node moments of the phase populations (phi, j, FP32 residual), rewritten
   // by every step
@@ -188,22 +192,30 @@ void refresh_args(nphase_lbm_t h) {
 hipError_t launch(nphase_lbm_t h, int mode, int side) {
   const int N = h->N, sa = h->prm.solve_all, model = h->prm.model;
   if (h->prec == NPHASE_FP64) {
+    StepArgs<double> a = h->a64[side];
+    a.first = h->t == 0;
     if (h->lat == NPHASE_D2Q9)
-      return launch_step<double, LAT_D2Q9>(N, sa, model, mode, h->a64[side], h->ntiles, h->stream);
-    return launch_step<double, LAT_D3Q19>(N, sa, model, mode, h->a64[side], h->ntiles, h->stream);
+      return launch_step<double, LAT_D2Q9>(N, sa, model, mode, a, h->ntiles, h->stream);
+    return launch_step<double, LAT_D3Q19>(N, sa, model, mode, a, h->ntiles, h->stream);
   }
+  StepArgs<float> a = h->a32[side];
+  a.first = h->t == 0;
   if (h->lat == NPHASE_D2Q9)
-    return launch_step<float, LAT_D2Q9>(N, sa, model, mode, h->a32[side], h->ntiles, h->stream);
-  return launch_step<float, LAT_D3Q19>(N, sa, model, mode, h->a32[side], h->ntiles, h->stream);
+    return launch_step<float, LAT_D2Q9>(N, sa, model, mode, a, h->ntiles, h->stream);
+  return launch_step<float, LAT_D3Q19>(N, sa, model, mode, a, h->ntiles, h->stream);
 }
 
 template <typename T, int LAT>
 hipError_t launch_mass(nphase_lbm_t h) {
   long long nb = (h->V + 255) / 256;
   const int nblk = (int)(nb < RED_BLOCKS ? nb : RED_BLOCKS);
-  hipLaunchKernelGGL((mass_partial_kernel<T, LAT>), dim3(nblk), dim3(256), 0, h->stream,
-                     (const T*)h->f[h->cur], (const T*)h->pm[h->cur], h->partial, h->N, h->NS,
-                     h->V);
+  if (LAT == LAT_D3Q19)
+    hipLaunchKernelGGL((mass_partial_mr_kernel<T>), dim3(nblk), dim3(256), 0, h->stream,
+                       (const T*)h->f[h->cur], h->partial, h->N, h->NS, h->V, RED_BLOCKS);
+  else
+    hipLaunchKernelGGL((mass_partial_kernel<T, LAT>), dim3(nblk), dim3(256), 0, h->stream,
+                       (const T*)h->f[h->cur], (const T*)h->pm[h->cur], h->partial, h->N, h->NS,
+                       h->V);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(mass_final_kernel, dim3(h->N), dim3(256), 0, h->stream,
@@ -221,8 +233,12 @@ template <typename T, int LAT>
 hipError_t launch_init(nphase_lbm_t h, const double* phi0) {
   const int nb = (int)((h->V + 255) / 256);
   const int s = h->cur;
-  hipLaunchKernelGGL((init_kernel<T, LAT>), dim3(nb), dim3(256), 0, h->stream, phi0, (T*)h->f[s],
-                     (T*)h->g[s], (T*)h->u[s], (T*)h->pm[s], (T*)h->mm, h->NS, h->V);
+  if (LAT == LAT_D3Q19)
+    hipLaunchKernelGGL((init_mr_kernel<T>), dim3(nb), dim3(256), 0, h->stream, phi0, (T*)h->f[s],
+                       (T*)h->g[s], (T*)h->u[s], (T*)h->mm, h->NS, h->V);
+  else
+    hipLaunchKernelGGL((init_kernel<T, LAT>), dim3(nb), dim3(256), 0, h->stream, phi0, (T*)h->f[s],
+                       (T*)h->g[s], (T*)h->u[s], (T*)h->pm[s], (T*)h->mm, h->NS, h->V);
   return hipGetLastError();
 }
 
@@ -343,6 +359,7 @@ int nphase_lbm_fields(nphase_lbm_t h, double* phi_dev, double* u_dev, double* p_
   double* sp = p_dev;
   if (h->prec == NPHASE_FP64) {
     StepArgs<double> a = h->a64[h->cur];
+    a.first = h->t == 0;
     a.phi_out = sphi; a.u_out = su; a.p_out = sp;
     a.f_dst = nullptr; a.g_dst = nullptr; a.u_dst = nullptr; a.pm_dst = nullptr;
     const int N = h->N, sa = h->prm.solve_all, model = h->prm.model;
@@ -352,6 +369,7 @@ int nphase_lbm_fields(nphase_lbm_t h, double* phi_dev, double* u_dev, double* p_
     HIPCHK(e, "fields kernel");
   } else {
     StepArgs<float> a = h->a32[h->cur];
+    a.first = h->t == 0;
     a.phi_out = sphi; a.u_out = su; a.p_out = sp;
     a.f_dst = nullptr; a.g_dst = nullptr; a.u_dst = nullptr; a.pm_dst = nullptr;
     const int N = h->N, sa = h->prm.solve_all, model = h->prm.model;
@@ -381,14 +399,20 @@ int nphase_lbm_check(nphase_lbm_t h, int* all_finite_host) {
   if (!h->inited) { h->err = "check before init"; return NPHASE_ESTATE; }
   hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, h->stream, h->flag_dev, 1);
   HIPCHK(hipGetLastError(), "zero kernel");
-  const long long n_u = (long long)h->D * h->V, n_pm = (long long)h->NS * h->V;
+  // phi^{t-1} lives in its own buffer (D2Q9) or in the moment-form state (D3Q19: the
+  // whole moment state is checked)
+  const bool mr = h->lat == NPHASE_D3Q19;
+  const long long n_u = (long long)h->D * h->V;
+  const long long n_pm = mr ? (long long)h->NS * (h->prec == NPHASE_FP64 ? MR<double>::N : MR<float>::N) * h->V
+                            : (long long)h->NS * h->V;
+  const void* pmp = mr ? h->f[h->cur] : h->pm[h->cur];
   const int nb = 1024;
   if (h->prec == NPHASE_FP64) {
     hipLaunchKernelGGL(finite_kernel<double>, dim3(nb), dim3(256), 0, h->stream, (const double*)h->u[h->cur], n_u, h->flag_dev);
-    hipLaunchKernelGGL(finite_kernel<double>, dim3(nb), dim3(256), 0, h->stream, (const double*)h->pm[h->cur], n_pm, h->flag_dev);
+    hipLaunchKernelGGL(finite_kernel<double>, dim3(nb), dim3(256), 0, h->stream, (const double*)pmp, n_pm, h->flag_dev);
   } else {
     hipLaunchKernelGGL(finite_kernel<float>, dim3(nb), dim3(256), 0, h->stream, (const float*)h->u[h->cur], n_u, h->flag_dev);
-    hipLaunchKernelGGL(finite_kernel<float>, dim3(nb), dim3(256), 0, h->stream, (const float*)h->pm[h->cur], n_pm, h->flag_dev);
+    hipLaunchKernelGGL(finite_kernel<float>, dim3(nb), dim3(256), 0, h->stream, (const float*)pmp, n_pm, h->flag_dev);
   }
   HIPCHK(hipGetLastError(), "finite kernel");
   int flag = 0;
@@ -407,10 +431,12 @@ int nphase_lbm_time(nphase_lbm_t h, int64_t* t_host) {
 
 static size_t state_payload(nphase_lbm_t h, size_t* parts) {
   const size_t ts = h->tsize;
-  parts[0] = (size_t)h->NS * h->Q * h->V * ts;
+  const bool mr = h->lat == NPHASE_D3Q19;
+  const size_t nmr = ts == 4 ? MR<float>::N : MR<double>::N;
+  parts[0] = (size_t)h->NS * (mr ? nmr : (size_t)h->Q) * h->V * ts;
   parts[1] = (size_t)(h->Q - 1) * h->V * ts;
   parts[2] = (size_t)h->D * h->V * ts;
-  parts[3] = (size_t)h->NS * h->V * ts;
+  parts[3] = mr ? 0 : (size_t)h->NS * h->V * ts;
   parts[4] = (size_t)h->D * h->V * ts;
   return parts[0] + parts[1] + parts[2] + parts[3] + parts[4];
 }
@@ -682,15 +708,17 @@ int nphase_lbm_adjoint_sigma(nphase_lbm_t h, void* adj_ws_dev, double* dL_dsigma
 
 int nphase_lbm_state64_bytes(nphase_lbm_t h, size_t* bytes_host) {
   if (!h || !bytes_host) return NPHASE_EINVAL;
-  size_t parts[5];
-  *bytes_host = ALIGN + state_payload(h, parts) / h->tsize * sizeof(double);
+  // f [NS][Q], g [Q-1], u [D], phi^{t-1} [NS], m_phi [D], FP64
+  const size_t words = (size_t)h->NS * h->Q + (h->Q - 1) + h->D + h->NS + h->D;
+  *bytes_host = ALIGN + words * (size_t)h->V * sizeof(double);
   return NPHASE_OK;
 }
 
 int nphase_lbm_save_state64(nphase_lbm_t h, void* state_dev) {
   int rc = check_handle(h);
   if (rc) return rc;
-  if (h->prec == NPHASE_FP64) return nphase_lbm_save_state(h, state_dev);
+  const bool mr = h->lat == NPHASE_D3Q19;
+  if (h->prec == NPHASE_FP64 && !mr) return nphase_lbm_save_state(h, state_dev);
   if (!state_dev) { h->err = "state buffer is NULL"; return NPHASE_EINVAL; }
   if (!h->inited) { h->err = "save before init"; return NPHASE_ESTATE; }
   rc = put_header(h, state_dev);
@@ -698,13 +726,19 @@ int nphase_lbm_save_state64(nphase_lbm_t h, void* state_dev) {
   const StatePtrs o = state_ptrs(h, state_dev);
   const int c = h->cur;
   const unsigned nb = (unsigned)((h->V + 255) / 256);
-  if (h->lat == NPHASE_D2Q9)
-    hipLaunchKernelGGL((state_to64_kernel<float, LAT_D2Q9>), dim3(nb), dim3(256), 0, h->stream,
+  const int first = h->t == 0;
+  if (mr && h->prec == NPHASE_FP64)
+    hipLaunchKernelGGL((mr_to_pop64_kernel<double>), dim3(nb), dim3(256), 0, h->stream,
+                       (const double*)h->f[c], (const double*)h->g[c], (const double*)h->u[c],
+                       (const double*)h->mm, o.f, o.g, o.u, o.pm, o.mm, h->NS, h->prm.nx,
+                       h->prm.ny, h->prm.nz, first);
+  else if (mr)
+    hipLaunchKernelGGL((mr_to_pop64_kernel<float>), dim3(nb), dim3(256), 0, h->stream,
                        (const float*)h->f[c], (const float*)h->g[c], (const float*)h->u[c],
-                       (const float*)h->pm[c], (const float*)h->mm, o.f, o.g, o.u, o.pm, o.mm,
-                       h->NS, h->V);
+                       (const float*)h->mm, o.f, o.g, o.u, o.pm, o.mm, h->NS, h->prm.nx,
+                       h->prm.ny, h->prm.nz, first);
   else
-    hipLaunchKernelGGL((state_to64_kernel<float, LAT_D3Q19>), dim3(nb), dim3(256), 0, h->stream,
+    hipLaunchKernelGGL((state_to64_kernel<float, LAT_D2Q9>), dim3(nb), dim3(256), 0, h->stream,
                        (const float*)h->f[c], (const float*)h->g[c], (const float*)h->u[c],
                        (const float*)h->pm[c], (const float*)h->mm, o.f, o.g, o.u, o.pm, o.mm,
                        h->NS, h->V);

@@ -1,11 +1,19 @@
-// D3Q19 time step: a moments pass and a fused z-marching collide-and-stream pass.
+// D3Q19 time step: a moments pass and a fused z-marching collide-and-stream pass, over a
+// moment representation of the phase-field populations.
 //
-// nphase_moments3d_kernel (one thread per node) reduces the post-stream phase populations
-// of every node to what the rest of the step uses of them (Sec. 3 macroscopic recovery):
-// phi_p = sum_i f_{i,p} and the first moments j_p = sum_i c_i f_{i,p}; FP32 also keeps the
-// exact rounding residual of phi = phi^{t-1} + sum f~.  Every later stage of the step uses
-// the populations only through these moments (the collisions are in closed form), so the
-// halo of the stencils reads 1 value per phase and node instead of Q.
+// State of an evolved set p at node x (slots of MR<T>): the post-collision populations of
+// the last step are exactly f*_i = w_i (phi + c_i . A) + [c_i on an axis] c_i . D / 2
+// (closed form of f - M^-1 S M (f - f^eq) + (I - M^-1 S M / 2) R, Sec. 3 with the Sec. 4
+// natural M and diagonal S), so x stores (phi, A, D) = 7 values instead of 19 populations;
+// phi is also the phi^{t-1} of the next step.  FP32 stores phi rounded plus its exact
+// rounding residual, which the rest population of the node carries (mass is kept).
+// Streaming is a pull: f_i(y) = f*_i(y - c_i) is rebuilt where it is used.
+//
+// nphase_moments3d_kernel (z-marching, LDS plane ring) rebuilds the pulled populations of
+// every node from its 19 upwind neighbours and reduces them to what the rest of the step uses
+// (Sec. 3 macroscopic recovery): phi_p = sum_i f_{i,p}, the first moments
+// j_p = sum_i c_i f_{i,p}, and in FP32 the exact rounding residual of phi.  At t = 0 the
+// state is the equilibrium f_i = w_i phi0 of the initial condition: phi = phi0, j = 0.
 //
 // nphase_step3d_kernel: a workgroup of 256 threads owns a TX x TY column tile (one thread
 // per column; 64 x 4 in FP64, 32 x 8 in FP32) and a run of ZR planes in z.  It marches through the run with a three-stage
@@ -16,7 +24,8 @@
 //                  ring, and the antisymmetric tensor m_phi u^- - u^- m_phi into a ring of
 //                  LDS planes (Sec. 2.1, Sec. 2.2, Sec. 3 closing paragraph);
 //   S3 plane z     correction force from that tensor, forces, u, P, the closed-form
-//                  moment-space collisions and push streaming (Sec. 2.2, Sec. 3).
+//                  moment-space collisions, written as (phi, A, D) at the own node, and
+//                  the push of the flow populations (Sec. 2.2, Sec. 3).
 // The own-node results of S2 are kept in registers for the S3 of the next iteration.  The
 // halo is recomputed only in x and y (FP64: 2.1x the phi loads for the 68 x 8 region
 // plane and 1.55x the S2 work for the 66 x 6 inner plane; FP32: 1.69x and 1.33x); in z
@@ -41,6 +50,14 @@ struct Z3Tile {
 };
 constexpr int Z3_ZR = 32;   // planes per workgroup run
 
+// Slots of the moment representation of one evolved set: [PHI] phi, [A + d] A_d,
+// [DD + d] D_d, and in FP32 [RES] the rounding residual of phi.  Layout f[NS][NMR][V].
+template <typename T>
+struct MR {
+  static constexpr int PHI = 0, A = 1, DD = 4, RES = 7;
+  static constexpr int N = sizeof(T) == 4 ? 8 : 7;
+};
+
 // Moments of one node, layout mo[NM][V]: [p] phi_p, [NS + p D + d] j_{p,d}, and for FP32
 // [NS + NS D + p] the two-sum residual (phi^{t-1} + sum f~) - phi of the rounded phi.
 template <typename T, int NS>
@@ -48,42 +65,158 @@ constexpr int n_moments() {
   return NS * 4 + (sizeof(T) == 4 ? NS : 0);
 }
 
+// Column tile and run of the moments pass: 64 x 4 columns, 32 planes.  It marches in z
+// per evolved set with a 3-plane LDS ring of the moment fields (tile + 1-node ring in x,y),
+// so every stored value is read from memory about 1.55 times (the x,y halo) instead of
+// once per neighbour that pulls from it.
+constexpr int M3_TX = 64, M3_TY = 4, M3_ZR = 32;
+
 template <typename T, int NS>
-__global__ void __launch_bounds__(NTHREADS) nphase_moments3d_kernel(const StepArgs<T> a) {
+__global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) nphase_moments3d_kernel(const StepArgs<T> a) {
   using L = Lattice<LAT_D3Q19>;
-  constexpr int D = 3, Q = 19;
+  constexpr int D = 3, Q = 19, NMR = MR<T>::N;
+  constexpr int NF = 7;   // phi, A, D: the fields pulled from neighbours
   constexpr bool DEV = sizeof(T) == 4;
+  constexpr int TX = M3_TX, TY = M3_TY, ZR = M3_ZR;
+  constexpr int RX = TX + 2, RY = TY + 2, RP = RX * RY;
+  __shared__ T s_mr[3][NF][RP];
+
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
   const size_t Vs = (size_t)a.V;
-  const size_t gl = (size_t)blockIdx.x * NTHREADS + threadIdx.x;
-  if (gl >= Vs) return;
-  const unsigned gi = (unsigned)gl;
-  auto LD = [&](const T* base, int comp) -> T { return (base + (size_t)comp * Vs)[gi]; };
-  auto ST = [&](T* base, int comp, T v) { (base + (size_t)comp * Vs)[gi] = v; };
+  const int t = threadIdx.x;
+  int tile;
+  {
+    const int b = blockIdx.x, nt = a.ntiles;
+    const int q = nt / 8, r8 = nt % 8, xcd = b % 8, loc = b / 8;
+    tile = xcd * q + (xcd < r8 ? xcd : r8) + loc;
+  }
+  const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY;
+  const int tx0 = (tile % ntx) * TX;
+  const int ty0 = ((tile / ntx) % nty) * TY;
+  const int z0 = (tile / (ntx * nty)) * ZR;
+  const int zend = (z0 + ZR < nz) ? z0 + ZR : nz;
+  const int lx = t % TX, ly = t / TX;
+  const int ox = tx0 + lx, oy = ty0 + ly;
+  const bool valid = ox < nx && oy < ny;
+  const size_t plane = (size_t)nx * ny;
+  const size_t col = (size_t)(valid ? ox : 0) + (size_t)nx * (valid ? oy : 0);
+  auto LD = [&](int comp, size_t node) -> T { return (a.f_src + (size_t)comp * Vs)[node]; };
+  auto ST = [&](int comp, size_t node, T v) { (a.mo + (size_t)comp * Vs)[node] = v; };
+
+  if (a.first) {
+    // initial equilibrium f_i = w_i phi0: phi = phi0 (FP32: rounded + residual), j = 0
+    if (!valid) return;
+    for (int z = z0; z < zend; ++z) {
+      const size_t gi = col + plane * z;
 #pragma unroll
-  for (int p = 0; p < NS; ++p) {
-    T v[Q];
+      for (int p = 0; p < NS; ++p) {
+        ST(p, gi, LD(p * NMR + MR<T>::PHI, gi));
 #pragma unroll
-    for (int i = 0; i < Q; ++i) v[i] = LD(a.f_src, p * Q + i);
-    T s = v[0];
-#pragma unroll
-    for (int i = 1; i < Q; ++i) s += v[i];
-    if constexpr (DEV) {
-      const T pm = LD(a.pm_src, p);
-      const T sum = pm + s;
-      const T bb = sum - pm;
-      ST(a.mo, NS * (1 + D) + p, (pm - (sum - bb)) + (s - bb));
-      s = sum;
-    }
-    ST(a.mo, p, s);
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-      T jj = T(0);
-#pragma unroll
-      for (int i = 1; i < Q; ++i) {
-        if (L::c(i, d) == 1) jj += v[i];
-        if (L::c(i, d) == -1) jj -= v[i];
+        for (int d = 0; d < D; ++d) ST(NS + p * D + d, gi, T(0));
+        if constexpr (DEV) ST(NS * (1 + D) + p, gi, LD(p * NMR + MR<T>::RES, gi));
       }
-      ST(a.mo, NS + p * D + d, jj);
+    }
+    return;
+  }
+
+  auto slot = [](int z) { const int r = z % 3; return r < 0 ? r + 3 : r; };
+  // Plane z of set p (tile + ring) is fetched into registers (PL values per thread) one
+  // iteration ahead and written to its ring slot after the compute, so the loads overlap
+  // the LDS work.  Positions past a ragged edge (columns no thread owns) wrap like the
+  // rest, so every load stays inside the grid.
+  constexpr int PL = (NF * RP + NTHREADS - 1) / NTHREADS;
+  T pre[PL];
+  unsigned poff[PL];   // in-plane node of each fetched value (fixed per workgroup)
+#pragma unroll
+  for (int j = 0; j < PL; ++j) {
+    const int k = t + j * NTHREADS;
+    const int r = (k < NF * RP ? k : 0) % RP;
+    poff[j] = (unsigned)wrap(tx0 - 1 + r % RX, nx) + (unsigned)nx * (unsigned)wrap(ty0 - 1 + r / RX, ny);
+  }
+  auto fetch_plane = [&](int p, int z) {
+    const size_t zoff = plane * (size_t)wrap(z, nz);
+#pragma unroll
+    for (int j = 0; j < PL; ++j) {
+      const int k = t + j * NTHREADS;
+      if (k < NF * RP) pre[j] = LD(p * NMR + k / RP, (size_t)poff[j] + zoff);
+    }
+  };
+  auto store_plane = [&](int z) {
+    const int sl = slot(z);
+#pragma unroll
+    for (int j = 0; j < PL; ++j) {
+      const int k = t + j * NTHREADS;
+      if (k < NF * RP) s_mr[sl][k / RP][k % RP] = pre[j];
+    }
+  };
+  const int rown = (lx + 1) + RX * (ly + 1);
+
+#pragma unroll 1
+  for (int p = 0; p < NS; ++p) {
+    __syncthreads();   // the previous set's last compute has read the ring
+    fetch_plane(p, z0 - 1);
+    store_plane(z0 - 1);
+    fetch_plane(p, z0);
+    store_plane(z0);
+    fetch_plane(p, z0 + 1);
+#pragma unroll 1
+    for (int z = z0; z < zend; ++z) {
+      store_plane(z + 1);   // its slot (plane z - 2) was last read before the previous barrier
+      __syncthreads();
+      if (z + 1 < zend) fetch_plane(p, z + 2);   // in flight during the compute of plane z
+      if (valid) {
+        const size_t gi = col + plane * z;
+        const T ph_own = s_mr[slot(z)][MR<T>::PHI][rown];
+        T s = T(0), jj[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) jj[d] = T(0);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          // f_i(y) = f*_i(y - c_i) = w_i (phi + c_i . A) + [axis] c_i . D / 2 at y - c_i
+          T fi;
+          if (i == 0) {
+            if constexpr (DEV) fi = LD(p * NMR + MR<T>::RES, gi);   // the rest carries the residual
+            else fi = T(L::w(0)) * ph_own;
+          } else {
+            const int sl = slot(z - L::c(i, 2));
+            const int rs = rown - L::c(i, 0) - RX * L::c(i, 1);
+            T cA = T(0), cD = T(0);
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+              if (L::c(i, d) == 1) cA += s_mr[sl][MR<T>::A + d][rs];
+              if (L::c(i, d) == -1) cA -= s_mr[sl][MR<T>::A + d][rs];
+            }
+            const T phs = s_mr[sl][MR<T>::PHI][rs];
+            // FP32: deviation from the rest weights of the node's own phi^{t-1}
+            if constexpr (DEV) fi = T(L::w(i)) * ((phs - ph_own) + cA);
+            else fi = T(L::w(i)) * (phs + cA);
+            if (cnorm2<L>(i) == 1) {
+#pragma unroll
+              for (int d = 0; d < D; ++d) {
+                if (L::c(i, d) == 1) cD += s_mr[sl][MR<T>::DD + d][rs];
+                if (L::c(i, d) == -1) cD -= s_mr[sl][MR<T>::DD + d][rs];
+              }
+              fi += T(0.5) * cD;
+            }
+          }
+          s = (i == 0) ? fi : s + fi;
+#pragma unroll
+          for (int d = 0; d < D; ++d) {
+            if (L::c(i, d) == 1) jj[d] += fi;
+            if (L::c(i, d) == -1) jj[d] -= fi;
+          }
+        }
+        if constexpr (DEV) {
+          const T sum = ph_own + s;
+          const T bb = sum - ph_own;
+          ST(NS * (1 + D) + p, gi, (ph_own - (sum - bb)) + (s - bb));
+          s = sum;
+        }
+        ST(p, gi, s);
+#pragma unroll
+        for (int d = 0; d < D; ++d) ST(NS + p * D + d, gi, jj[d]);
+      }
+      __syncthreads();   // plane z - 1's slot is reloaded next
     }
   }
 }
@@ -98,7 +231,7 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 2 : 1) nphase_step3
   constexpr int TX = Z3Tile<T>::TX, TY = Z3Tile<T>::TY, ZR = Z3_ZR;
   constexpr int RX = TX + 4, RY = TY + 4, RP = RX * RY;   // region plane (2-node ring)
   constexpr int IX = TX + 2, IY = TY + 2, IP = IX * IY;   // inner plane (1-node ring)
-  constexpr int PHR = DEV ? 5 : 3;                        // phi ring depth
+  constexpr int PHR = DEV ? 4 : 3;                        // phi ring depth
   constexpr int WR = 3;                                   // tensor ring depth
   constexpr T CS2 = T(1) / T(3);
   // LDS budget: two workgroups per CU for FP32, one for FP64; the Model B pair fractions
@@ -385,7 +518,7 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 2 : 1) nphase_step3
     // phi^{t-1} of the evolved sets
     T phm[N];
 #pragma unroll
-    for (int p = 0; p < NS; ++p) phm[p] = LD(a.pm_src, p, g_own);
+    for (int p = 0; p < NS; ++p) phm[p] = LD(a.f_src, p * MR<T>::N + MR<T>::PHI, g_own);
     if constexpr (!SA) {
       T rest = phm[0];
 #pragma unroll
@@ -520,31 +653,16 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 2 : 1) nphase_step3
           A[d] = T(3) * ph * u[d] + T(0.5) * Zp[d];
           Dp[d] = (T(1) - a.s1) * (j_own[d] - ph * u[d] + T(0.5) * CS2 * Zp[d]);
         }
+        // post-collision populations in moment form at the own node (pulled by the next
+        // step's moments pass): f*_i = w_i (phi + c_i . A) + [axis] c_i . D / 2
+        constexpr int NMR = MR<T>::N;
+        ST(a.f_dst, p * NMR + MR<T>::PHI, g_own, ph);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-          T cA = T(0), cD = T(0);
-#pragma unroll
-          for (int d = 0; d < D; ++d) {
-            if (L::c(i, d) == 1) { cA += A[d]; cD += Dp[d]; }
-            if (L::c(i, d) == -1) { cA -= A[d]; cD -= Dp[d]; }
-          }
-          const T wi = T(L::w(i));
-          T fs;
-          if constexpr (DEV) {
-            if (i == 0) {
-              fs = wi * cA + res_own;
-            } else {
-              const T dphi =
-                  ph - s_phi[p][ring_of(zs3 + L::c(i, 2), PHR)][rown + roff2(i)];
-              fs = wi * (dphi + cA);
-            }
-          } else {
-            fs = wi * (ph + cA);
-          }
-          if (cnorm2<L>(i) == 1) fs += T(0.5) * cD;
-          ST(a.f_dst, p * Q + i, dest(i), fs);
+        for (int d = 0; d < D; ++d) {
+          ST(a.f_dst, p * NMR + MR<T>::A + d, g_own, A[d]);
+          ST(a.f_dst, p * NMR + MR<T>::DD + d, g_own, Dp[d]);
         }
-        ST(a.pm_dst, p, g_own, ph);
+        if constexpr (DEV) ST(a.f_dst, p * NMR + MR<T>::RES, g_own, res_own);
       }
       T T2[D][D];
       T trT = T(0);
@@ -607,6 +725,113 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 2 : 1) nphase_step3
         ST(a.mm, d, g_own, mpc[d]);
       }
     }
+  }
+}
+
+// ---- moment-representation state outside the step ----------------------------------------
+
+// Initial state f_i = w_i phi0 (the equilibrium at rest): phi slot = phi0 (FP32: rounded,
+// with the exact residual phi0 - fl(phi0) in its slot), A = D = 0; g, u, m_phi = 0.  The
+// moments pass reads it with the first-step flag (phi = phi0, j = 0).
+template <typename T>
+__global__ void __launch_bounds__(256)
+    init_mr_kernel(const double* __restrict__ phi0, T* __restrict__ mr, T* __restrict__ g,
+                   T* __restrict__ u, T* __restrict__ mm, int NS, long long V) {
+  constexpr int D = 3, Q = 19, NMR = MR<T>::N;
+  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= V) return;
+  for (int p = 0; p < NS; ++p) {
+    const double ph = phi0[(long long)p * V + x];
+    const T stored = (T)ph;
+    for (int k = 0; k < NMR; ++k) mr[(long long)(p * NMR + k) * V + x] = T(0);
+    mr[(long long)(p * NMR + MR<T>::PHI) * V + x] = stored;
+    if (sizeof(T) == 4) mr[(long long)(p * NMR + MR<T>::RES) * V + x] = (T)(ph - (double)stored);
+  }
+  for (int i = 1; i < Q; ++i) g[(long long)(i - 1) * V + x] = T(0);
+  for (int d = 0; d < D; ++d) {
+    u[(long long)d * V + x] = T(0);
+    mm[(long long)d * V + x] = T(0);
+  }
+}
+
+// Per-block FP64 partial sums of every phase.  The populations a moment state stands for
+// sum to the stored phi over the domain (sum_i w_i = 1, sum_i w_i c_i = 0, the axis D
+// terms cancel in pairs), plus the FP32 residuals.  partial[p * RED_BLOCKS + block].
+template <typename T>
+__global__ void __launch_bounds__(256)
+    mass_partial_mr_kernel(const T* __restrict__ mr, double* __restrict__ partial, int N,
+                           int NS, long long V, int red_blocks) {
+  constexpr int NMR = MR<T>::N;
+  __shared__ double red[MAXN][256];
+  double acc[MAXN];
+  for (int p = 0; p < MAXN; ++p) acc[p] = 0.0;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < V; x += stride) {
+    double rest = 0.0;
+    for (int p = 0; p < NS; ++p) {
+      double s = (double)mr[(long long)(p * NMR + MR<T>::PHI) * V + x];
+      if (sizeof(T) == 4) s += (double)mr[(long long)(p * NMR + MR<T>::RES) * V + x];
+      acc[p] += s;
+      rest += s;
+    }
+    if (NS < N) acc[N - 1] += 1.0 - rest;
+  }
+  for (int p = 0; p < N; ++p) red[p][threadIdx.x] = acc[p];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int p = 0; p < N; ++p) red[p][threadIdx.x] += red[p][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int p = 0; p < N; ++p) partial[p * red_blocks + blockIdx.x] = red[p][0];
+}
+
+// The moment state as FP64 post-stream populations (the layout the adjoint reads):
+// f_i(y) = f*_i(y - c_i) rebuilt in FP64 (FP32: plus the residual on the rest population),
+// phi^{t-1} = the stored phi, g, u, m_phi widened.  first: f_i = w_i (phi + residual).
+template <typename T>
+__global__ void __launch_bounds__(256)
+    mr_to_pop64_kernel(const T* __restrict__ mr, const T* __restrict__ g, const T* __restrict__ u,
+                       const T* __restrict__ mm, double* __restrict__ f64, double* __restrict__ g64,
+                       double* __restrict__ u64, double* __restrict__ pm64, double* __restrict__ mm64,
+                       int NS, int nx, int ny, int nz, int first) {
+  using L = Lattice<LAT_D3Q19>;
+  constexpr int D = 3, Q = 19, NMR = MR<T>::N;
+  const long long V = (long long)nx * ny * nz;
+  const long long gl = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gl >= V) return;
+  const int x = (int)(gl % nx), y = (int)((gl / nx) % ny), z = (int)(gl / ((long long)nx * ny));
+  auto at = [&](int p, int k, long long node) -> double {
+    return (double)mr[(long long)(p * NMR + k) * V + node];
+  };
+  for (int p = 0; p < NS; ++p) {
+    const double res = sizeof(T) == 4 ? at(p, MR<T>::RES, gl) : 0.0;
+    pm64[(long long)p * V + gl] = at(p, MR<T>::PHI, gl);
+    for (int i = 0; i < Q; ++i) {
+      double v;
+      if (first) {
+        v = L::w(i) * (at(p, MR<T>::PHI, gl) + res);
+      } else {
+        const int xs = (x - L::c(i, 0) + nx) % nx, ys = (y - L::c(i, 1) + ny) % ny;
+        const int zs = (z - L::c(i, 2) + nz) % nz;
+        const long long sn = xs + (long long)nx * (ys + (long long)ny * zs);
+        double cA = 0.0, cD = 0.0;
+        for (int d = 0; d < D; ++d) {
+          cA += L::c(i, d) * at(p, MR<T>::A + d, sn);
+          cD += L::c(i, d) * at(p, MR<T>::DD + d, sn);
+        }
+        v = L::w(i) * (at(p, MR<T>::PHI, sn) + cA);
+        if (cnorm2<L>(i) == 1) v += 0.5 * cD;
+        if (i == 0) v += res;
+      }
+      f64[(long long)(p * Q + i) * V + gl] = v;
+    }
+  }
+  for (int i = 1; i < Q; ++i) g64[(long long)(i - 1) * V + gl] = (double)g[(long long)(i - 1) * V + gl];
+  for (int d = 0; d < D; ++d) {
+    u64[(long long)d * V + gl] = (double)u[(long long)d * V + gl];
+    mm64[(long long)d * V + gl] = (double)mm[(long long)d * V + gl];
   }
 }
 

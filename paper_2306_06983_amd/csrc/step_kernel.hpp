@@ -57,6 +57,7 @@ struct StepArgs {
   T* pm_dst;
   T* mm;
   T* mo;             // D3Q19: per-node moments of the phase populations [NM][V]
+  int first;         // D3Q19: 1 while the state is the initial equilibrium (t = 0)
   double* phi_out;   // fields mode: [N][V]
   double* u_out;     // fields mode: [D][V]
   double* p_out;     // fields mode: [V]

@@ -42,15 +42,16 @@ def test_workspace_bytes_model(lib):
     assert rc == B.NPHASE_OK and n32 < n
 
 
-@pytest.mark.parametrize("precision,b,nm", [("fp64", 8, 4), ("fp32", 4, 5)])
-def test_workspace_bytes_d3q19(lib, precision, b, nm):
-    # state buffers plus the per-node moment scratch (phi_p, j_p; FP32 also the residual)
+@pytest.mark.parametrize("precision,b,nmr,nm", [("fp64", 8, 7, 4), ("fp32", 4, 8, 5)])
+def test_workspace_bytes_d3q19(lib, precision, b, nmr, nm):
+    # D3Q19 state: the phase field in moment form (phi, A, D per set; FP32 also the
+    # residual), g, u (both double-buffered), m_phi, plus the per-node moment scratch
     cfg, _ = inputs.spheres(n=32, scale=0.125)
     p = B.make_params(cfg, precision)
     rc, n = _ws(lib, p)
     assert rc == B.NPHASE_OK
     V, NS, Q, d = 32 ** 3, 3, 19, 3
-    words = 2 * (NS * Q + (Q - 1) + d + NS) + d + nm * NS
+    words = 2 * (NS * nmr + (Q - 1) + d) + d + nm * NS
     assert words * V * b <= n < words * V * b + 200_000
 
 

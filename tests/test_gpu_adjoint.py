@@ -2,8 +2,9 @@
 
 * one step: for a state with every phase present (smooth random mixture, so no normal or
   pair-fraction guard is active) and random adjoint vectors, <lambda^t, ds> equals
-  <lambda^{t+1}, (Step(s + h ds) - Step(s - h ds)) / 2h> for perturbations of each state
-  component separately (f, g, u^{t-1}, phi^{t-1}, m_phi^{t-1}), D2Q9 and D3Q19, A and B;
+  <lambda^{t+1}, (Step(s + h ds) - Step(s - h ds)) / 2h> with Step the oracle's step,
+  for perturbations of each state component separately (f, g, u^{t-1}, phi^{t-1},
+  m_phi^{t-1}), D2Q9 and D3Q19, A and B;
 * whole runs: dL/dsigma_pq and directional dL/dphi0 of a phase-field misfit against
   central finite differences of the oracle (<= 1e-4 relative);
 * checkpoint-every-k recomputation gives the same gradient as one segment (bitwise).
@@ -46,12 +47,40 @@ def _mixture(lattice, shape, N, seed, model="B", rho=None, solve_all=False):
     return cfg, phi
 
 
+def _buffer_to_oracle(C, buf64):
+    """FP64 state buffer (save_state64 layout) -> oracle state dict."""
+    from oracle.nphase import RHO0
+    v = buf64.detach().cpu().numpy()
+    lat, sh, NS, d = C.lat, C.shape, C.NS, C.lat.d
+    V = int(np.prod(sh))
+    o = 0
+    def take(n):
+        nonlocal o
+        out = v[o:o + n * V].reshape((n,) + sh)
+        o += n * V
+        return out.copy()
+    f = take(NS * lat.Q).reshape((NS, lat.Q) + sh)
+    g = np.concatenate([np.full((1,) + sh, RHO0), take(lat.Q - 1)], axis=0)  # g_0 is inert
+    u = take(d)
+    pm = take(NS)
+    mm = take(d)
+    return {"f": f, "g": g, "u_prev": u, "phi_prev": pm, "mphi_prev": mm, "rho_bar": 0.0, "t": 1}
+
+
+def _oracle_to_vector(st):
+    parts = [st["f"].reshape(-1), st["g"][1:].reshape(-1), st["u_prev"].reshape(-1),
+             st["phi_prev"].reshape(-1), st["mphi_prev"].reshape(-1)]
+    return np.concatenate(parts)
+
+
 def _dot_test(cfg, phi, comp, h=1e-6, seed=0):
+    """<adjoint_step(s)^T lam, ds> against <lam, central difference of the oracle's step
+    along ds> at a state s taken from the GPU run (in the FP64 population layout)."""
     import torch
     from paper_2306_06983_amd import binding as B
     sim = B.Sim(cfg, "fp64").init(phi)
     sim.step(4)                                  # non-zero velocity and history
-    s0 = sim.save_state()
+    s0 = sim.save_state64()
     nb = s0.numel()
     payload = (nb - HDR) // 8
     V = int(np.prod(sim.grid))
@@ -72,24 +101,21 @@ def _dot_test(cfg, phi, comp, h=1e-6, seed=0):
     ds = torch.zeros(payload, dtype=torch.float64)
     lo, hi = off[comp]
     ds[lo:hi] = torch.randn(hi - lo, generator=g, dtype=torch.float64)
-    ds = ds.to(sim.device)
-    base = s0[HDR:].view(torch.float64)
+    base = s0[HDR:].view(torch.float64).cpu()
     scale = base[lo:hi].abs().max().item()
     step = h * max(scale, 1e-3)
+    C = O.Config(cfg)
 
     def fwd(sign):
-        sp = s0.clone()
-        sp[HDR:].view(torch.float64).add_(sign * step * ds)
-        sim.load_state(sp)
-        sim.step(1)
-        return sim.save_state()[HDR:].view(torch.float64).clone()
+        st = _buffer_to_oracle(C, base + sign * step * ds)
+        return _oracle_to_vector(O.step(C, st, 1))
 
-    fd = ((fwd(+1) - fwd(-1)) / (2 * step) * lam_v).sum().item()
+    fd = float(((fwd(+1) - fwd(-1)) / (2 * step) * lam_v.cpu().numpy()).sum())
     ws = sim.adjoint_workspace()
     sim.adjoint_sigma(ws, reset=True, read=False)
     out = torch.zeros_like(lam)
     sim.adjoint_step(s0, lam, out, ws)
-    adj = (out[HDR:].view(torch.float64) * ds).sum().item()
+    adj = (out[HDR:].view(torch.float64).cpu() * ds).sum().item()
     torch.cuda.synchronize()
     sim.close()
     return fd, adj
