@@ -30,7 +30,6 @@ struct nphase_lbm_s {
   void* f[2] = {nullptr, nullptr};
   void* g[2] = {nullptr, nullptr};
   void* u[2] = {nullptr, nullptr};
-  void* pm[2] = {nullptr, nullptr};
   void* mm = nullptr;
   void* mo = nullptr;   // D3Q19 moment scratch (not part of the state)
   double* partial = nullptr;
@@ -55,7 +54,7 @@ constexpr double CS2 = 1.0 / 3.0;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-  size_t f, g, u, pm, mm, mo, partial, mass, flag, total;
+  size_t f, g, u, mm, mo, partial, mass, flag, total;
 };
 
 // sizes of every buffer for a validated parameter set
@@ -67,14 +66,13 @@ Layout layout_of(const nphase_lbm_params& p) {
   const size_t V = (size_t)p.nx * (size_t)p.ny * (size_t)p.nz;
   const size_t ts = p.precision == NPHASE_FP64 ? 8 : 4;
   Layout L;
-  // D3Q19 keeps the phase field in moment form (phi, A, D per set; FP32 also the residual),
+  // the phase field is kept in moment form (phi, A, D per set; FP32 also the residual),
   // whose phi slot is the next step's phi^{t-1}: no separate phi^{t-1} buffers
-  const bool mr = p.lattice == NPHASE_D3Q19;
-  const size_t nmr = ts == 4 ? MR<float>::N : MR<double>::N;
-  L.f = align_up((size_t)NS * (mr ? nmr : (size_t)Q) * V * ts);
+  const size_t nmr = 1 + 2 * (size_t)D + (ts == 4 ? 1 : 0);
+  L.f = align_up((size_t)NS * nmr * V * ts);
+  (void)Q;
   L.g = align_up((size_t)(Q - 1) * V * ts);
   L.u = align_up((size_t)D * V * ts);
-  L.pm = mr ? 0 : align_up((size_t)NS * V * ts);
   L.mm = align_up((size_t)D * V * ts);
   // D3Q19: per-node moments of the phase populations (phi, j, FP32 residual), rewritten
   // by every step
@@ -82,7 +80,7 @@ Layout layout_of(const nphase_lbm_params& p) {
   L.partial = align_up((size_t)MAXN * RED_BLOCKS * sizeof(double));
   L.mass = align_up(MAXN * sizeof(double));
   L.flag = align_up(sizeof(int) * 4);
-  L.total = 2 * (L.f + L.g + L.u + L.pm) + L.mm + L.mo + L.partial + L.mass + L.flag;
+  L.total = 2 * (L.f + L.g + L.u) + L.mm + L.mo + L.partial + L.mass + L.flag;
   return L;
 }
 
@@ -151,8 +149,6 @@ void fill_args(nphase_lbm_t h, StepArgs<T>* out) {
     a.g_dst = (T*)h->g[dst];
     a.u_src = (const T*)h->u[side];
     a.u_dst = (T*)h->u[dst];
-    a.pm_src = (const T*)h->pm[side];
-    a.pm_dst = (T*)h->pm[dst];
     a.mm = (T*)h->mm;
     a.mo = (T*)h->mo;
     a.nx = p.nx;
@@ -209,13 +205,8 @@ template <typename T, int LAT>
 hipError_t launch_mass(nphase_lbm_t h) {
   long long nb = (h->V + 255) / 256;
   const int nblk = (int)(nb < RED_BLOCKS ? nb : RED_BLOCKS);
-  if (LAT == LAT_D3Q19)
-    hipLaunchKernelGGL((mass_partial_mr_kernel<T>), dim3(nblk), dim3(256), 0, h->stream,
-                       (const T*)h->f[h->cur], h->partial, h->N, h->NS, h->V, RED_BLOCKS);
-  else
-    hipLaunchKernelGGL((mass_partial_kernel<T, LAT>), dim3(nblk), dim3(256), 0, h->stream,
-                       (const T*)h->f[h->cur], (const T*)h->pm[h->cur], h->partial, h->N, h->NS,
-                       h->V);
+  hipLaunchKernelGGL((mass_partial_mr_kernel<T, LAT>), dim3(nblk), dim3(256), 0, h->stream,
+                     (const T*)h->f[h->cur], h->partial, h->N, h->NS, h->V, RED_BLOCKS);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(mass_final_kernel, dim3(h->N), dim3(256), 0, h->stream,
@@ -233,12 +224,8 @@ template <typename T, int LAT>
 hipError_t launch_init(nphase_lbm_t h, const double* phi0) {
   const int nb = (int)((h->V + 255) / 256);
   const int s = h->cur;
-  if (LAT == LAT_D3Q19)
-    hipLaunchKernelGGL((init_mr_kernel<T>), dim3(nb), dim3(256), 0, h->stream, phi0, (T*)h->f[s],
-                       (T*)h->g[s], (T*)h->u[s], (T*)h->mm, h->NS, h->V);
-  else
-    hipLaunchKernelGGL((init_kernel<T, LAT>), dim3(nb), dim3(256), 0, h->stream, phi0, (T*)h->f[s],
-                       (T*)h->g[s], (T*)h->u[s], (T*)h->pm[s], (T*)h->mm, h->NS, h->V);
+  hipLaunchKernelGGL((init_mr_kernel<T, LAT>), dim3(nb), dim3(256), 0, h->stream, phi0,
+                     (T*)h->f[s], (T*)h->g[s], (T*)h->u[s], (T*)h->mm, h->NS, h->V);
   return hipGetLastError();
 }
 
@@ -288,7 +275,6 @@ int nphase_lbm_create(const nphase_lbm_params* params, void* workspace_dev, size
   for (int s = 0; s < 2; ++s) { h->f[s] = q; q += L.f; }
   for (int s = 0; s < 2; ++s) { h->g[s] = q; q += L.g; }
   for (int s = 0; s < 2; ++s) { h->u[s] = q; q += L.u; }
-  for (int s = 0; s < 2; ++s) { h->pm[s] = q; q += L.pm; }
   h->mm = q; q += L.mm;
   h->mo = L.mo ? q : nullptr; q += L.mo;
   h->partial = (double*)q; q += L.partial;
@@ -361,7 +347,7 @@ int nphase_lbm_fields(nphase_lbm_t h, double* phi_dev, double* u_dev, double* p_
     StepArgs<double> a = h->a64[h->cur];
     a.first = h->t == 0;
     a.phi_out = sphi; a.u_out = su; a.p_out = sp;
-    a.f_dst = nullptr; a.g_dst = nullptr; a.u_dst = nullptr; a.pm_dst = nullptr;
+    a.f_dst = nullptr; a.g_dst = nullptr; a.u_dst = nullptr;
     const int N = h->N, sa = h->prm.solve_all, model = h->prm.model;
     hipError_t e = h->lat == NPHASE_D2Q9
                        ? launch_step<double, LAT_D2Q9>(N, sa, model, MODE_FIELDS, a, h->ntiles, h->stream)
@@ -371,7 +357,7 @@ int nphase_lbm_fields(nphase_lbm_t h, double* phi_dev, double* u_dev, double* p_
     StepArgs<float> a = h->a32[h->cur];
     a.first = h->t == 0;
     a.phi_out = sphi; a.u_out = su; a.p_out = sp;
-    a.f_dst = nullptr; a.g_dst = nullptr; a.u_dst = nullptr; a.pm_dst = nullptr;
+    a.f_dst = nullptr; a.g_dst = nullptr; a.u_dst = nullptr;
     const int N = h->N, sa = h->prm.solve_all, model = h->prm.model;
     hipError_t e = h->lat == NPHASE_D2Q9
                        ? launch_step<float, LAT_D2Q9>(N, sa, model, MODE_FIELDS, a, h->ntiles, h->stream)
@@ -399,13 +385,10 @@ int nphase_lbm_check(nphase_lbm_t h, int* all_finite_host) {
   if (!h->inited) { h->err = "check before init"; return NPHASE_ESTATE; }
   hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, h->stream, h->flag_dev, 1);
   HIPCHK(hipGetLastError(), "zero kernel");
-  // phi^{t-1} lives in its own buffer (D2Q9) or in the moment-form state (D3Q19: the
-  // whole moment state is checked)
-  const bool mr = h->lat == NPHASE_D3Q19;
+  // phi^{t-1} lives in the moment-form state: the whole moment state is checked
   const long long n_u = (long long)h->D * h->V;
-  const long long n_pm = mr ? (long long)h->NS * (h->prec == NPHASE_FP64 ? MR<double>::N : MR<float>::N) * h->V
-                            : (long long)h->NS * h->V;
-  const void* pmp = mr ? h->f[h->cur] : h->pm[h->cur];
+  const long long n_pm = (long long)h->NS * (1 + 2 * h->D + (h->prec == NPHASE_FP64 ? 0 : 1)) * h->V;
+  const void* pmp = h->f[h->cur];
   const int nb = 1024;
   if (h->prec == NPHASE_FP64) {
     hipLaunchKernelGGL(finite_kernel<double>, dim3(nb), dim3(256), 0, h->stream, (const double*)h->u[h->cur], n_u, h->flag_dev);
@@ -431,19 +414,18 @@ int nphase_lbm_time(nphase_lbm_t h, int64_t* t_host) {
 
 static size_t state_payload(nphase_lbm_t h, size_t* parts) {
   const size_t ts = h->tsize;
-  const bool mr = h->lat == NPHASE_D3Q19;
-  const size_t nmr = ts == 4 ? MR<float>::N : MR<double>::N;
-  parts[0] = (size_t)h->NS * (mr ? nmr : (size_t)h->Q) * h->V * ts;
+  const size_t nmr = 1 + 2 * (size_t)h->D + (ts == 4 ? 1 : 0);
+  // moment form (its phi slot is phi^{t-1}), g, u^{t-1}, m_phi^{t-1}
+  parts[0] = (size_t)h->NS * nmr * h->V * ts;
   parts[1] = (size_t)(h->Q - 1) * h->V * ts;
   parts[2] = (size_t)h->D * h->V * ts;
-  parts[3] = mr ? 0 : (size_t)h->NS * h->V * ts;
-  parts[4] = (size_t)h->D * h->V * ts;
-  return parts[0] + parts[1] + parts[2] + parts[3] + parts[4];
+  parts[3] = (size_t)h->D * h->V * ts;
+  return parts[0] + parts[1] + parts[2] + parts[3];
 }
 
 int nphase_lbm_state_bytes(nphase_lbm_t h, size_t* bytes_host) {
   if (!h || !bytes_host) return NPHASE_EINVAL;
-  size_t parts[5];
+  size_t parts[4];
   *bytes_host = ALIGN + state_payload(h, parts);
   return NPHASE_OK;
 }
@@ -470,13 +452,13 @@ int nphase_lbm_save_state(nphase_lbm_t h, void* state_dev) {
   if (rc) return rc;
   if (!state_dev) { h->err = "state buffer is NULL"; return NPHASE_EINVAL; }
   if (!h->inited) { h->err = "save before init"; return NPHASE_ESTATE; }
-  size_t parts[5];
+  size_t parts[4];
   state_payload(h, parts);
   rc = put_header(h, state_dev);
   if (rc) return rc;
   char* q = (char*)state_dev + ALIGN;
-  const void* src[5] = {h->f[h->cur], h->g[h->cur], h->u[h->cur], h->pm[h->cur], h->mm};
-  for (int k = 0; k < 5; ++k) {
+  const void* src[4] = {h->f[h->cur], h->g[h->cur], h->u[h->cur], h->mm};
+  for (int k = 0; k < 4; ++k) {
     HIPCHK(hipMemcpyAsync(q, src[k], parts[k], hipMemcpyDeviceToDevice, h->stream), "save copy");
     q += parts[k];
   }
@@ -487,15 +469,15 @@ int nphase_lbm_load_state(nphase_lbm_t h, const void* state_dev) {
   int rc = check_handle(h);
   if (rc) return rc;
   if (!state_dev) { h->err = "state buffer is NULL"; return NPHASE_EINVAL; }
-  size_t parts[5];
+  size_t parts[4];
   state_payload(h, parts);
   StateHeader hdr;
   HIPCHK(hipMemcpyAsync(&hdr, state_dev, sizeof(hdr), hipMemcpyDeviceToHost, h->stream), "load header");
   HIPCHK(hipStreamSynchronize(h->stream), "load header sync");
   if (hdr.magic != 0x4e5048415345) { h->err = "not a state buffer"; return NPHASE_EINVAL; }
   const char* q = (const char*)state_dev + ALIGN;
-  void* dst[5] = {h->f[h->cur], h->g[h->cur], h->u[h->cur], h->pm[h->cur], h->mm};
-  for (int k = 0; k < 5; ++k) {
+  void* dst[4] = {h->f[h->cur], h->g[h->cur], h->u[h->cur], h->mm};
+  for (int k = 0; k < 4; ++k) {
     HIPCHK(hipMemcpyAsync(dst[k], q, parts[k], hipMemcpyDeviceToDevice, h->stream), "load copy");
     q += parts[k];
   }
@@ -717,8 +699,6 @@ int nphase_lbm_state64_bytes(nphase_lbm_t h, size_t* bytes_host) {
 int nphase_lbm_save_state64(nphase_lbm_t h, void* state_dev) {
   int rc = check_handle(h);
   if (rc) return rc;
-  const bool mr = h->lat == NPHASE_D3Q19;
-  if (h->prec == NPHASE_FP64 && !mr) return nphase_lbm_save_state(h, state_dev);
   if (!state_dev) { h->err = "state buffer is NULL"; return NPHASE_EINVAL; }
   if (!h->inited) { h->err = "save before init"; return NPHASE_ESTATE; }
   rc = put_header(h, state_dev);
@@ -727,21 +707,26 @@ int nphase_lbm_save_state64(nphase_lbm_t h, void* state_dev) {
   const int c = h->cur;
   const unsigned nb = (unsigned)((h->V + 255) / 256);
   const int first = h->t == 0;
-  if (mr && h->prec == NPHASE_FP64)
-    hipLaunchKernelGGL((mr_to_pop64_kernel<double>), dim3(nb), dim3(256), 0, h->stream,
-                       (const double*)h->f[c], (const double*)h->g[c], (const double*)h->u[c],
-                       (const double*)h->mm, o.f, o.g, o.u, o.pm, o.mm, h->NS, h->prm.nx,
-                       h->prm.ny, h->prm.nz, first);
-  else if (mr)
-    hipLaunchKernelGGL((mr_to_pop64_kernel<float>), dim3(nb), dim3(256), 0, h->stream,
-                       (const float*)h->f[c], (const float*)h->g[c], (const float*)h->u[c],
-                       (const float*)h->mm, o.f, o.g, o.u, o.pm, o.mm, h->NS, h->prm.nx,
-                       h->prm.ny, h->prm.nz, first);
-  else
-    hipLaunchKernelGGL((state_to64_kernel<float, LAT_D2Q9>), dim3(nb), dim3(256), 0, h->stream,
-                       (const float*)h->f[c], (const float*)h->g[c], (const float*)h->u[c],
-                       (const float*)h->pm[c], (const float*)h->mm, o.f, o.g, o.u, o.pm, o.mm,
-                       h->NS, h->V);
+  const nphase_lbm_params& p = h->prm;
+  if (h->prec == NPHASE_FP64) {
+    const double *f = (const double*)h->f[c], *g = (const double*)h->g[c];
+    const double *u = (const double*)h->u[c], *mm = (const double*)h->mm;
+    if (h->lat == NPHASE_D2Q9)
+      hipLaunchKernelGGL((mr_to_pop64_kernel<double, LAT_D2Q9>), dim3(nb), dim3(256), 0, h->stream,
+                         f, g, u, mm, o.f, o.g, o.u, o.pm, o.mm, h->NS, p.nx, p.ny, p.nz, first);
+    else
+      hipLaunchKernelGGL((mr_to_pop64_kernel<double, LAT_D3Q19>), dim3(nb), dim3(256), 0, h->stream,
+                         f, g, u, mm, o.f, o.g, o.u, o.pm, o.mm, h->NS, p.nx, p.ny, p.nz, first);
+  } else {
+    const float *f = (const float*)h->f[c], *g = (const float*)h->g[c];
+    const float *u = (const float*)h->u[c], *mm = (const float*)h->mm;
+    if (h->lat == NPHASE_D2Q9)
+      hipLaunchKernelGGL((mr_to_pop64_kernel<float, LAT_D2Q9>), dim3(nb), dim3(256), 0, h->stream,
+                         f, g, u, mm, o.f, o.g, o.u, o.pm, o.mm, h->NS, p.nx, p.ny, p.nz, first);
+    else
+      hipLaunchKernelGGL((mr_to_pop64_kernel<float, LAT_D3Q19>), dim3(nb), dim3(256), 0, h->stream,
+                         f, g, u, mm, o.f, o.g, o.u, o.pm, o.mm, h->NS, p.nx, p.ny, p.nz, first);
+  }
   HIPCHK(hipGetLastError(), "save state64");
   return NPHASE_OK;
 }

@@ -50,14 +50,6 @@ struct Z3Tile {
 };
 constexpr int Z3_ZR = 32;   // planes per workgroup run
 
-// Slots of the moment representation of one evolved set: [PHI] phi, [A + d] A_d,
-// [DD + d] D_d, and in FP32 [RES] the rounding residual of phi.  Layout f[NS][NMR][V].
-template <typename T>
-struct MR {
-  static constexpr int PHI = 0, A = 1, DD = 4, RES = 7;
-  static constexpr int N = sizeof(T) == 4 ? 8 : 7;
-};
-
 // Moments of one node, layout mo[NM][V]: [p] phi_p, [NS + p D + d] j_{p,d}, and for FP32
 // [NS + NS D + p] the two-sum residual (phi^{t-1} + sum f~) - phi of the rounded phi.
 template <typename T, int NS>
@@ -732,20 +724,22 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 2 : 1) nphase_step3
 
 // Initial state f_i = w_i phi0 (the equilibrium at rest): phi slot = phi0 (FP32: rounded,
 // with the exact residual phi0 - fl(phi0) in its slot), A = D = 0; g, u, m_phi = 0.  The
-// moments pass reads it with the first-step flag (phi = phi0, j = 0).
-template <typename T>
+// step reads it with the first-step flag (phi = phi0, j = 0).
+template <typename T, int LAT>
 __global__ void __launch_bounds__(256)
     init_mr_kernel(const double* __restrict__ phi0, T* __restrict__ mr, T* __restrict__ g,
                    T* __restrict__ u, T* __restrict__ mm, int NS, long long V) {
-  constexpr int D = 3, Q = 19, NMR = MR<T>::N;
+  using L = Lattice<LAT>;
+  constexpr int D = L::D, Q = L::Q;
+  using S = MR<T, D>;
   const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= V) return;
   for (int p = 0; p < NS; ++p) {
     const double ph = phi0[(long long)p * V + x];
     const T stored = (T)ph;
-    for (int k = 0; k < NMR; ++k) mr[(long long)(p * NMR + k) * V + x] = T(0);
-    mr[(long long)(p * NMR + MR<T>::PHI) * V + x] = stored;
-    if (sizeof(T) == 4) mr[(long long)(p * NMR + MR<T>::RES) * V + x] = (T)(ph - (double)stored);
+    for (int k = 0; k < S::N; ++k) mr[(long long)(p * S::N + k) * V + x] = T(0);
+    mr[(long long)(p * S::N + S::PHI) * V + x] = stored;
+    if (sizeof(T) == 4) mr[(long long)(p * S::N + S::RES) * V + x] = (T)(ph - (double)stored);
   }
   for (int i = 1; i < Q; ++i) g[(long long)(i - 1) * V + x] = T(0);
   for (int d = 0; d < D; ++d) {
@@ -756,12 +750,12 @@ __global__ void __launch_bounds__(256)
 
 // Per-block FP64 partial sums of every phase.  The populations a moment state stands for
 // sum to the stored phi over the domain (sum_i w_i = 1, sum_i w_i c_i = 0, the axis D
-// terms cancel in pairs), plus the FP32 residuals.  partial[p * RED_BLOCKS + block].
-template <typename T>
+// terms cancel in pairs), plus the FP32 residuals.  partial[p * red_blocks + block].
+template <typename T, int LAT>
 __global__ void __launch_bounds__(256)
     mass_partial_mr_kernel(const T* __restrict__ mr, double* __restrict__ partial, int N,
                            int NS, long long V, int red_blocks) {
-  constexpr int NMR = MR<T>::N;
+  using S = MR<T, Lattice<LAT>::D>;
   __shared__ double red[MAXN][256];
   double acc[MAXN];
   for (int p = 0; p < MAXN; ++p) acc[p] = 0.0;
@@ -769,8 +763,8 @@ __global__ void __launch_bounds__(256)
   for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < V; x += stride) {
     double rest = 0.0;
     for (int p = 0; p < NS; ++p) {
-      double s = (double)mr[(long long)(p * NMR + MR<T>::PHI) * V + x];
-      if (sizeof(T) == 4) s += (double)mr[(long long)(p * NMR + MR<T>::RES) * V + x];
+      double s = (double)mr[(long long)(p * S::N + S::PHI) * V + x];
+      if (sizeof(T) == 4) s += (double)mr[(long long)(p * S::N + S::RES) * V + x];
       acc[p] += s;
       rest += s;
     }
@@ -790,38 +784,39 @@ __global__ void __launch_bounds__(256)
 // The moment state as FP64 post-stream populations (the layout the adjoint reads):
 // f_i(y) = f*_i(y - c_i) rebuilt in FP64 (FP32: plus the residual on the rest population),
 // phi^{t-1} = the stored phi, g, u, m_phi widened.  first: f_i = w_i (phi + residual).
-template <typename T>
+template <typename T, int LAT>
 __global__ void __launch_bounds__(256)
     mr_to_pop64_kernel(const T* __restrict__ mr, const T* __restrict__ g, const T* __restrict__ u,
                        const T* __restrict__ mm, double* __restrict__ f64, double* __restrict__ g64,
                        double* __restrict__ u64, double* __restrict__ pm64, double* __restrict__ mm64,
                        int NS, int nx, int ny, int nz, int first) {
-  using L = Lattice<LAT_D3Q19>;
-  constexpr int D = 3, Q = 19, NMR = MR<T>::N;
+  using L = Lattice<LAT>;
+  constexpr int D = L::D, Q = L::Q;
+  using S = MR<T, D>;
   const long long V = (long long)nx * ny * nz;
   const long long gl = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (gl >= V) return;
   const int x = (int)(gl % nx), y = (int)((gl / nx) % ny), z = (int)(gl / ((long long)nx * ny));
   auto at = [&](int p, int k, long long node) -> double {
-    return (double)mr[(long long)(p * NMR + k) * V + node];
+    return (double)mr[(long long)(p * S::N + k) * V + node];
   };
   for (int p = 0; p < NS; ++p) {
-    const double res = sizeof(T) == 4 ? at(p, MR<T>::RES, gl) : 0.0;
-    pm64[(long long)p * V + gl] = at(p, MR<T>::PHI, gl);
+    const double res = sizeof(T) == 4 ? at(p, S::RES, gl) : 0.0;
+    pm64[(long long)p * V + gl] = at(p, S::PHI, gl);
     for (int i = 0; i < Q; ++i) {
       double v;
       if (first) {
-        v = L::w(i) * (at(p, MR<T>::PHI, gl) + res);
+        v = L::w(i) * (at(p, S::PHI, gl) + res);
       } else {
         const int xs = (x - L::c(i, 0) + nx) % nx, ys = (y - L::c(i, 1) + ny) % ny;
         const int zs = (z - L::c(i, 2) + nz) % nz;
         const long long sn = xs + (long long)nx * (ys + (long long)ny * zs);
         double cA = 0.0, cD = 0.0;
         for (int d = 0; d < D; ++d) {
-          cA += L::c(i, d) * at(p, MR<T>::A + d, sn);
-          cD += L::c(i, d) * at(p, MR<T>::DD + d, sn);
+          cA += L::c(i, d) * at(p, S::A + d, sn);
+          cD += L::c(i, d) * at(p, S::DD + d, sn);
         }
-        v = L::w(i) * (at(p, MR<T>::PHI, sn) + cA);
+        v = L::w(i) * (at(p, S::PHI, sn) + cA);
         if (cnorm2<L>(i) == 1) v += 0.5 * cD;
         if (i == 0) v += res;
       }

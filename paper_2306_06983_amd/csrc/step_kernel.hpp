@@ -53,8 +53,6 @@ struct StepArgs {
   T* g_dst;
   const T* u_src;
   T* u_dst;
-  const T* pm_src;
-  T* pm_dst;
   T* mm;
   T* mo;             // D3Q19: per-node moments of the phase populations [NM][V]
   int first;         // D3Q19: 1 while the state is the initial equilibrium (t = 0)
@@ -166,6 +164,19 @@ __device__ __forceinline__ void chemical_potentials(const A& a, const T* ph, con
   }
 }
 
+// Moment form of the post-collision populations of one evolved set (the state the step
+// reads and writes): f*_i = w_i (phi + c_i . A) + [c_i on an axis] c_i . D / 2, the closed
+// form of f - M^-1 S M (f - f^eq) + (I - M^-1 S M / 2) R (Sec. 3; natural M and diagonal S,
+// Sec. 4 intro), with A = 3 phi u + Z / 2, D = (1 - 1/tau_f)(j - phi u + c_s^2 Z / 2),
+// Z = 3 d_t(phi u) + R_p.  Slots: [PHI] phi, [A + d] A_d, [DD + d] D_d, and in FP32 [RES]
+// the exact rounding residual of phi, which the rest population of the node carries.
+// The stored phi is the next step's phi^{t-1}.  Layout f[NS][N][V].
+template <typename T, int D = 3>
+struct MR {
+  static constexpr int PHI = 0, A = 1, DD = 1 + D, RES = 1 + 2 * D;
+  static constexpr int N = 1 + 2 * D + (sizeof(T) == 4 ? 1 : 0);
+};
+
 // Model B pairwise fraction phi_pq = phi_p / (phi_p + phi_q), 1/2 where both vanish
 template <typename T>
 __device__ __forceinline__ T pair_fraction(T pp, T pq) {
@@ -192,13 +203,22 @@ __global__ void __launch_bounds__(TileShape<LAT>::NT) nphase_step_kernel(const S
   constexpr int NW = (D == 3) ? 3 : 1;   // independent components of the antisymmetric tensor
   constexpr T CS2 = T(1) / T(3);
 
-  // Model B pair fractions are staged in LDS when they fit a 64 KiB budget, otherwise
-  // they are recomputed from phi at every stencil point.
-  constexpr bool PF_LDS =
-      (MODEL == MODEL_B) && (sizeof(T) * ((NS + NP) * NR + NW * NI) <= 65536);
+  // LDS: the moment form of the tile + 3-node halo (read by stage 1 only) shares its
+  // space with the Model B pair fractions and the antisymmetric tensor (written from the
+  // end of stage 1 on); phi of the tile + 2-node halo has its own array.
+  using S = MR<T, D>;
+  constexpr int NF = 1 + 2 * D;   // fields staged per set (the FP32 residual is read where used)
+  constexpr int EX = TX + 6, EY = TY + 6, EZ = (D == 3) ? TZ + 6 : 1;
+  constexpr int NE = EX * EY * EZ;
+  constexpr bool PF_LDS = MODEL == MODEL_B;
+  constexpr int NPL = PF_LDS ? NP : 0;
+  constexpr size_t MR_BYTES = sizeof(T) * NS * NF * NE;
+  constexpr size_t PW_BYTES = sizeof(T) * (NPL * NR + NW * NI);
+  __shared__ __align__(16) unsigned char s_raw[MR_BYTES > PW_BYTES ? MR_BYTES : PW_BYTES];
   __shared__ T s_phi[NS][NR];
-  __shared__ T s_pf[PF_LDS ? NP : 1][PF_LDS ? NR : 1];
-  __shared__ T s_w[NW][NI];
+  T(*s_mr)[NF][NE] = reinterpret_cast<T(*)[NF][NE]>(s_raw);
+  T(*s_pf)[NR] = reinterpret_cast<T(*)[NR]>(s_raw);
+  T(*s_w)[NI] = reinterpret_cast<T(*)[NI]>(s_raw + sizeof(T) * NPL * NR);
 
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const long long V = a.V;
@@ -248,96 +268,120 @@ __global__ void __launch_bounds__(TileShape<LAT>::NT) nphase_step_kernel(const S
 
   // ---------------------------------------------------------------- stage 1
   T j_own[NS][D];
-  T pm_own[NS];
+  T pm_own[NS];    // phi^{t-1} of the own node (the stored phi)
   T res_own[NS];   // FP32: exact rounding residual of phi = phi^{t-1} + sum f~ (own node)
-  // populations (and FP32 phi^{t-1}) of the evolved sets at one node
-  auto load_node = [&](long long gi, T (&v)[NS][Q], T (&pmv)[NS]) {
+  // stage 0: moment form of the tile + 3-node halo into LDS (each thread computes the
+  // node index once and loads every field of that node)
+  for (int e = t; e < NE; e += NTH) {
+    const int ex = e % EX, ey = (e / EX) % EY, ez = e / (EX * EY);
+    const int gx = wrap(tx0 - 3 + ex, nx), gy = wrap(ty0 - 3 + ey, ny);
+    const int gz = (D == 3) ? wrap(tz0 - 3 + ez, nz) : 0;
+    const unsigned gi = (unsigned)gx + (unsigned)nx * ((unsigned)gy + (unsigned)ny * (unsigned)gz);
+#pragma unroll
+    for (int p = 0; p < NS; ++p)
+#pragma unroll
+      for (int f = 0; f < NF; ++f) s_mr[p][f][e] = LD(a.f_src, p * S::N + f, gi);
+  }
+  __syncthreads();
+  // phi (and for the own node j, the residual, phi^{t-1}) of region node r = (rx, ry, rz):
+  // the pulled populations f_i = f*_i(x - c_i) rebuilt from the moment form of the
+  // upwind neighbours (at t = 0 the initial equilibrium: phi = phi0, j = 0)
+  auto stage1 = [&](int r, int rx, int ry, int rz, long long gi, bool own) {
+    const int e = (rx + 1) + EX * ((ry + 1) + EY * (D == 3 ? rz + 1 : 0));
 #pragma unroll
     for (int p = 0; p < NS; ++p) {
+      const T ph_own = s_mr[p][S::PHI][e];
+      T res = T(0);
+      if constexpr (DEV) res = LD(a.f_src, p * S::N + S::RES, (unsigned)gi);
+      T s = T(0), jj[D];
 #pragma unroll
-      for (int i = 0; i < Q; ++i) v[p][i] = LD(a.f_src, p * Q + i, (unsigned)gi);
-      if constexpr (DEV) pmv[p] = LD(a.pm_src, p, (unsigned)gi);
-    }
-  };
-  auto stage1 = [&](int r, const T (&v)[NS][Q], const T (&pmv)[NS], bool own) {
-    T ph[N];
+      for (int d = 0; d < D; ++d) jj[d] = T(0);
+      if (a.first) {
+        if constexpr (DEV) s = res;
+        else s = ph_own;
+      } else {
 #pragma unroll
-    for (int p = 0; p < NS; ++p) {
-      T s = v[p][0];
+        for (int i = 0; i < Q; ++i) {
+          T fi;
+          if (i == 0) {
+            if constexpr (DEV) fi = res;   // the rest population carries the residual
+            else fi = T(L::w(0)) * ph_own;
+          } else {
+            const int es = e - L::c(i, 0) - EX * (L::c(i, 1) + EY * L::c(i, 2));
+            T cA = T(0), cD = T(0);
 #pragma unroll
-      for (int i = 1; i < Q; ++i) s += v[p][i];
+            for (int d = 0; d < D; ++d) {
+              if (L::c(i, d) == 1) cA += s_mr[p][S::A + d][es];
+              if (L::c(i, d) == -1) cA -= s_mr[p][S::A + d][es];
+            }
+            const T phs = s_mr[p][S::PHI][es];
+            // FP32: deviation from the rest weights of the node's own phi^{t-1}
+            if constexpr (DEV) fi = T(L::w(i)) * ((phs - ph_own) + cA);
+            else fi = T(L::w(i)) * (phs + cA);
+            if (cnorm2<L>(i) == 1) {
+#pragma unroll
+              for (int d = 0; d < D; ++d) {
+                if (L::c(i, d) == 1) cD += s_mr[p][S::DD + d][es];
+                if (L::c(i, d) == -1) cD -= s_mr[p][S::DD + d][es];
+              }
+              fi += T(0.5) * cD;
+            }
+          }
+          s = (i == 0) ? fi : s + fi;
+          if (own) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+              if (L::c(i, d) == 1) jj[d] += fi;
+              if (L::c(i, d) == -1) jj[d] -= fi;
+            }
+          }
+        }
+      }
       if constexpr (DEV) {
-        const T pm = pmv[p];
-        const T sum = pm + s;
+        // two-sum: (phi^{t-1} + s) - phi exactly; it is carried into the next state by the
+        // rest population of this node so that the stored state keeps the mass it had
+        const T sum = ph_own + s;
         if (own) {
-          // two-sum: (pm + s) - sum exactly; it is re-injected into the rest deviation
-          // written by this node so that the stored state keeps the mass it had
-          const T bb = sum - pm;
-          res_own[p] = (pm - (sum - bb)) + (s - bb);
-          pm_own[p] = pm;
+          const T bb = sum - ph_own;
+          res_own[p] = (ph_own - (sum - bb)) + (s - bb);
         }
         s = sum;
       }
-      ph[p] = s;
       s_phi[p][r] = s;
       if (own) {
+        pm_own[p] = ph_own;
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-          T jj = T(0);
-#pragma unroll
-          for (int i = 1; i < Q; ++i) {
-            if (L::c(i, d) == 1) jj += v[p][i];
-            if (L::c(i, d) == -1) jj -= v[p][i];
-          }
-          j_own[p][d] = jj;
-        }
-      }
-    }
-    if constexpr (!SA) {
-      T rest = ph[0];
-#pragma unroll
-      for (int p = 1; p < NS; ++p) rest += ph[p];
-      ph[N - 1] = T(1) - rest;
-    }
-    if constexpr (PF_LDS) {
-      int k = 0;
-#pragma unroll
-      for (int p = 0; p < N; ++p) {
-#pragma unroll
-        for (int q = p + 1; q < N; ++q) {
-          s_pf[k][r] = pair_fraction(ph[p], ph[q]);
-          ++k;
-        }
+        for (int d = 0; d < D; ++d) j_own[p][d] = jj[d];
       }
     }
   };
+  stage1(r_own, lx + 2, ly + 2, lz + HZ, g_own, true);
   {
     constexpr int NRING = NR - NTH;
-    T vo[NS][Q], pmo[NS];
-    load_node(g_own, vo, pmo);
-    if constexpr (DEV && NRING <= NTH) {
-      // FP32: the ring node's loads (at most one per thread) are issued before the own
-      // node is reduced, so that both are in flight together
-      const bool ring = t < NRING;
-      T vr[NS][Q], pmr[NS];
-      int rr = 0;
-      if (ring) {
-        int rx, ry, rz;
-        ring_coord<2, RX, RY, RZ>(t, rx, ry, rz);
-        rr = rx + RX * (ry + RY * rz);
-        load_node(region_gidx(rx, ry, rz), vr, pmr);
+    for (int k = t; k < NRING; k += NTH) {
+      int rx, ry, rz;
+      ring_coord<2, RX, RY, RZ>(k, rx, ry, rz);
+      stage1(rx + RX * (ry + RY * rz), rx, ry, rz, DEV ? region_gidx(rx, ry, rz) : 0, false);
+    }
+  }
+  // the moment form is dead from here on: its space takes the pair fractions and tensor
+  __syncthreads();
+  if constexpr (PF_LDS) {
+    for (int r = t; r < NR; r += NTH) {
+      T ph[N];
+#pragma unroll
+      for (int p = 0; p < NS; ++p) ph[p] = s_phi[p][r];
+      if constexpr (!SA) {
+        T rest = ph[0];
+#pragma unroll
+        for (int p = 1; p < NS; ++p) rest += ph[p];
+        ph[N - 1] = T(1) - rest;
       }
-      stage1(r_own, vo, pmo, true);
-      if (ring) stage1(rr, vr, pmr, false);
-    } else {
-      stage1(r_own, vo, pmo, true);
-      for (int k = t; k < NRING; k += NTH) {
-        int rx, ry, rz;
-        ring_coord<2, RX, RY, RZ>(k, rx, ry, rz);
-        T vr[NS][Q], pmr[NS];
-        load_node(region_gidx(rx, ry, rz), vr, pmr);
-        stage1(rx + RX * (ry + RY * rz), vr, pmr, false);
-      }
+      int k = 0;
+#pragma unroll
+      for (int p = 0; p < N; ++p)
+#pragma unroll
+        for (int q = p + 1; q < N; ++q, ++k) s_pf[k][r] = pair_fraction(ph[p], ph[q]);
     }
   }
   __syncthreads();
@@ -603,8 +647,7 @@ __global__ void __launch_bounds__(TileShape<LAT>::NT) nphase_step_kernel(const S
   T phm[N];
 #pragma unroll
   for (int p = 0; p < NS; ++p) {
-    if constexpr (DEV) phm[p] = pm_own[p];
-    else phm[p] = LD(a.pm_src, p, (unsigned)g_own);
+    phm[p] = pm_own[p];
   }
   if constexpr (!SA) {
     T rest = phm[0];
@@ -655,7 +698,9 @@ __global__ void __launch_bounds__(TileShape<LAT>::NT) nphase_step_kernel(const S
 
     // ---- phase-field collision (closed form of f - M^-1 S M (f - f^eq) + (I - M^-1 S M/2) R)
     //   f*_i = w_i [phi + c_i.(3 phi u + Z/2)] + [axis i] c_i.D / 2,
-    //   Z = 3 d_t(phi u) + R_p,  D = (1 - s1)(j - phi u + c_s^2 Z / 2)
+    //   Z = 3 d_t(phi u) + R_p,  D = (1 - s1)(j - phi u + c_s^2 Z / 2),
+    // stored in moment form (phi, A = 3 phi u + Z/2, D) at the own node; the next step
+    // pulls the populations from it
 #pragma unroll
     for (int p = 0; p < NS; ++p) {
       const T ph = phi_own[p];
@@ -666,31 +711,13 @@ __global__ void __launch_bounds__(TileShape<LAT>::NT) nphase_step_kernel(const S
         A[d] = T(3) * ph * u[d] + T(0.5) * Zp[d];
         Dp[d] = (T(1) - a.s1) * (j_own[p][d] - ph * u[d] + T(0.5) * CS2 * Zp[d]);
       }
+      ST(a.f_dst, p * S::N + S::PHI, (unsigned)g_own, ph);
 #pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        T cA = T(0), cD = T(0);
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-          if (L::c(i, d) == 1) { cA += A[d]; cD += Dp[d]; }
-          if (L::c(i, d) == -1) { cA -= A[d]; cD -= Dp[d]; }
-        }
-        const T wi = T(L::w(i));
-        T fs;
-        if constexpr (DEV) {
-          // deviation from the rest weights of the destination's phi (= its next phi^{t-1})
-          if (i == 0) {
-            fs = wi * cA + res_own[p];
-          } else {
-            const T dphi = ph - s_phi[p][r_own + roff(i)];
-            fs = wi * (dphi + cA);
-          }
-        } else {
-          fs = wi * (ph + cA);
-        }
-        if (cnorm2<L>(i) == 1) fs += T(0.5) * cD;
-        ST(a.f_dst, p * Q + i, dest(i), fs);
+      for (int d = 0; d < D; ++d) {
+        ST(a.f_dst, p * S::N + S::A + d, (unsigned)g_own, A[d]);
+        ST(a.f_dst, p * S::N + S::DD + d, (unsigned)g_own, Dp[d]);
       }
-      ST(a.pm_dst, p, (unsigned)g_own, ph);
+      if constexpr (DEV) ST(a.f_dst, p * S::N + S::RES, (unsigned)g_own, res_own[p]);
     }
 
     // ---- flow collision: g* = g^eq + F_i/2 + (1 - s2) M^-1 [second-order rows of

@@ -33,8 +33,10 @@ def test_workspace_bytes_model(lib):
     p = B.make_params(cfg)
     rc, n = _ws(lib, p)
     assert rc == B.NPHASE_OK
+    # state: the phase field in moment form (phi, A, D per set), g, u (double-buffered),
+    # m_phi
     V, NS, Q, d = 64 * 64, 2, 9, 2
-    state = 2 * (NS * Q + (Q - 1) + d + NS) + d
+    state = 2 * (NS * (1 + 2 * d) + (Q - 1) + d) + d
     assert n >= state * V * 8
     assert n < state * V * 8 + 200_000
     p32 = B.make_params(cfg, "fp32")

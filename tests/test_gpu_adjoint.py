@@ -280,30 +280,42 @@ def test_adjoint_full_size_two_discs():
 
 
 def test_state64_export():
-    """save_state64: FP64 handles write exactly the save_state bytes; FP32 handles write the
-    FP64 populations f~ + w_i phi^{t-1}, whose per-phase sums reproduce the FP64 mass of the
-    FP32 state and which stay within the FP32 parity bar of the FP64 run's state."""
+    """save_state64 writes the FP64 post-stream populations the moment-form state stands
+    for: at t = 0 the initial equilibrium w_i phi0; later, populations whose per-node sums
+    are the phase fields of fields() and whose domain sums are mass(); the FP32 handle's
+    export stays within the FP32 parity bar of the FP64 run's."""
     import torch
+    from oracle.lattice import d2q9
     from paper_2306_06983_amd import binding as B
     cfg, phi, _ = _loss_setup("B", steps=1)
-    s64 = B.Sim(cfg, "fp64").init(phi)
-    s64.step(30)
-    a = s64.save_state()
-    b = s64.save_state64()
-    # header fields (t, rho_bar, magic: 24 bytes; the rest of the 256 is padding) + payload
-    assert a.numel() == b.numel() and torch.equal(a[:24], b[:24]) and torch.equal(a[HDR:], b[HDR:])
-    s32 = B.Sim(cfg, "fp32").init(phi)
-    s32.step(30)
-    c = s32.save_state64()
-    assert c.numel() == a.numel()
     V = cfg["nx"] * cfg["ny"]
     NS, Q = cfg["n_phases"] - 1, 9
-    f64 = a[HDR:].view(torch.float64)[:NS * Q * V].view(NS, Q, V)
-    f32 = c[HDR:].view(torch.float64)[:NS * Q * V].view(NS, Q, V)
+    w = torch.tensor(d2q9().w, dtype=torch.float64, device="cuda:0")
+    phi_t = torch.tensor(phi, dtype=torch.float64, device="cuda:0").reshape(cfg["n_phases"], V)
+
+    def pops(buf):
+        return buf[HDR:].view(torch.float64)[:NS * Q * V].view(NS, Q, V)
+
+    for prec in ("fp64", "fp32"):
+        s0 = B.Sim(cfg, prec).init(phi)
+        f0 = pops(s0.save_state64())
+        ref = w[None, :, None] * phi_t[:NS, None, :]
+        assert float((f0 - ref).abs().max().item()) <= 1e-15
+        s0.close()
+    s64 = B.Sim(cfg, "fp64").init(phi)
+    s64.step(30)
+    f64 = pops(s64.save_state64())
+    ph = s64.fields()[0].reshape(cfg["n_phases"], V)
+    assert float((f64.sum(1) - ph[:NS]).abs().max().item()) <= 1e-13
+    m = s64.mass()
+    assert np.allclose(f64.sum(dim=(1, 2)).cpu().numpy(), m[:NS], rtol=1e-12, atol=0)
+    s32 = B.Sim(cfg, "fp32").init(phi)
+    s32.step(30)
+    f32 = pops(s32.save_state64())
     m32 = s32.mass()
     assert np.allclose(f32.sum(dim=(1, 2)).cpu().numpy(), m32[:NS], rtol=1e-12, atol=0)
     d = float((f32.sum(1) - f64.sum(1)).abs().max().item())
-    print(f"  30 steps: max |phi(fp32 export) - phi(fp64)| = {d:.2e}")
+    print(f"  30 steps: max |phi(fp32 export) - phi(fp64 export)| = {d:.2e}")
     assert d <= 2e-5
     s64.close()
     s32.close()
