@@ -89,12 +89,11 @@ typedef struct {
 
 /* Bytes of device workspace for this parameter set: both state buffers, the reduction
  * scratch and, for D3Q19, a per-node moment scratch of 4 NS (FP32: 5 NS) values that
- * every step rewrites.  State: D2Q9 keeps the phase-field populations f [NS][9] and
- * phi^{t-1} [NS]; D3Q19 keeps each evolved set in moment form, (phi, A, D) [NS][7] (FP32:
- * [NS][8] with the rounding residual of phi), from which the post-collision populations
- * are exactly f*_i = w_i (phi + c_i . A) + [c_i on an axis] c_i . D / 2 (the closed form
- * of the Sec. 3 collision with the Sec. 4 natural M and diagonal S), pulled by the next
- * step; its phi is the next step's phi^{t-1}.  Both keep g [Q-1], u^{t-1}, m_phi^{t-1}. */
+ * every step rewrites.  State: each evolved set in moment form, (phi, A, D) [NS][1+2d]
+ * (FP32: [NS][2+2d] with the rounding residual of phi), from which the post-collision
+ * populations are exactly f*_i = w_i (phi + c_i . A) + [c_i on an axis] c_i . D / 2 (the
+ * closed form of the Sec. 3 collision with the Sec. 4 natural M and diagonal S), pulled by
+ * the next step; its phi is the next step's phi^{t-1}.  Also g [Q-1], u^{t-1}, m_phi^{t-1}. */
 int nphase_lbm_workspace_bytes(const nphase_lbm_params *params, size_t *bytes_host);
 
 /* Validate and copy the parameters, carve the caller's workspace and bind the stream.
@@ -111,9 +110,10 @@ int nphase_lbm_create(const nphase_lbm_params *params, void *workspace_dev, size
 int nphase_lbm_init(nphase_lbm_t h, const double *phi0_dev);
 
 /* Advance nsteps >= 0 time steps (state read from one buffer, collided and streamed into
- * the other): one fused kernel per step on D2Q9 (populations pushed); on D3Q19 a moments
- * kernel (pulls the populations from the moment-form state and reduces them to phi_p,
- * j_p) followed by the fused z-marching collide-and-stream kernel.  Asynchronous. */
+ * the other; phase populations pulled from the moment form, flow populations pushed): one
+ * fused kernel per step on D2Q9; on D3Q19 a moments kernel (pulls the phase populations and
+ * reduces them to phi_p, j_p) followed by the fused z-marching collide-and-stream kernel.
+ * Asynchronous on the stream. */
 int nphase_lbm_step(nphase_lbm_t h, int64_t nsteps);
 
 /* Macroscopic fields at the current time T without changing the state (FP64, device):
@@ -143,10 +143,10 @@ int nphase_lbm_load_state(nphase_lbm_t h, const void *state_dev);
 
 /* The current state as the FP64 post-stream populations it stands for (256-byte header,
  * then f [NS][Q], g [Q-1], u^{t-1} [D], phi^{t-1} [NS], m_phi^{t-1} [D]; FP64):
- * state64_bytes gives its size.  D2Q9 FP64 handles: identical to save_state.  D2Q9 FP32:
- * f_i = f~_i + w_i phi^{t-1} evaluated in FP64, the other fields widened.  D3Q19: the
- * populations rebuilt from the moment form (f_i(y) = f*_i(y - c_i); at t = 0 the initial
- * equilibrium w_i phi0), in FP64.  The adjoint entry points read and write this layout.
+ * state64_bytes gives its size: the phase populations rebuilt from the moment form in FP64
+ * (f_i(y) = f*_i(y - c_i), FP32 with the residual on the rest population; at t = 0 the
+ * initial equilibrium w_i phi0), phi^{t-1} = the stored phi, the other fields widened.  The
+ * adjoint entry points read and write this layout.
  * Synchronises once for the header like save_state; the payload is written async.
  * Such a buffer is not accepted by load_state of an FP32 handle. */
 int nphase_lbm_state64_bytes(nphase_lbm_t h, size_t *bytes_host);
