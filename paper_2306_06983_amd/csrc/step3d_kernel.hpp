@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) nphase_momen
 }
 
 template <typename T, int N, bool SA, int MODEL, int MODE>
-__global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 2 : 1) nphase_step3d_kernel(const StepArgs<T> a) {
+__global__ void __launch_bounds__(NTHREADS, 2) nphase_step3d_kernel(const StepArgs<T> a) {
   using L = Lattice<LAT_D3Q19>;
   constexpr int D = 3, Q = 19;
   constexpr int NS = SA ? N : N - 1;
@@ -226,9 +226,10 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 2 : 1) nphase_step3
   constexpr int PHR = DEV ? 4 : 3;                        // phi ring depth
   constexpr int WR = 3;                                   // tensor ring depth
   constexpr T CS2 = T(1) / T(3);
-  // LDS budget: two workgroups per CU for FP32, one for FP64; the Model B pair fractions
-  // are staged when they fit, else recomputed at every stencil point.
-  constexpr int BUDGET = DEV ? 81920 : 162816;
+  // LDS budget: two workgroups (2 waves per SIMD) per CU in both precisions; the Model B
+  // pair fractions are staged when they fit, else recomputed at every stencil point
+  // (FP64: two waves per SIMD with the recomputation beat one wave with staged fractions)
+  constexpr int BUDGET = 81920;
   constexpr int BASE = sizeof(T) * (NS * PHR * RP + 3 * WR * IP);
   constexpr bool PF_LDS = (MODEL == MODEL_B) && BASE + (int)sizeof(T) * NP * 3 * RP <= BUDGET;
 
