@@ -272,15 +272,21 @@ __global__ void __launch_bounds__(TileShape<LAT>::NT) nphase_step_kernel(const S
   T res_own[NS];   // FP32: exact rounding residual of phi = phi^{t-1} + sum f~ (own node)
   // stage 0: moment form of the tile + 3-node halo into LDS (each thread computes the
   // node index once and loads every field of that node)
-  for (int e = t; e < NE; e += NTH) {
-    const int ex = e % EX, ey = (e / EX) % EY, ez = e / (EX * EY);
-    const int gx = wrap(tx0 - 3 + ex, nx), gy = wrap(ty0 - 3 + ey, ny);
-    const int gz = (D == 3) ? wrap(tz0 - 3 + ez, nz) : 0;
-    const unsigned gi = (unsigned)gx + (unsigned)nx * ((unsigned)gy + (unsigned)ny * (unsigned)gz);
+  // (a fixed trip count, so that all loads of a thread are in flight together)
+  constexpr int NEL = (NE + NTH - 1) / NTH;
 #pragma unroll
-    for (int p = 0; p < NS; ++p)
+  for (int j = 0; j < NEL; ++j) {
+    const int e = t + j * NTH;
+    if (e < NE) {
+      const int ex = e % EX, ey = (e / EX) % EY, ez = e / (EX * EY);
+      const int gx = wrap(tx0 - 3 + ex, nx), gy = wrap(ty0 - 3 + ey, ny);
+      const int gz = (D == 3) ? wrap(tz0 - 3 + ez, nz) : 0;
+      const unsigned gi = (unsigned)gx + (unsigned)nx * ((unsigned)gy + (unsigned)ny * (unsigned)gz);
 #pragma unroll
-      for (int f = 0; f < NF; ++f) s_mr[p][f][e] = LD(a.f_src, p * S::N + f, gi);
+      for (int p = 0; p < NS; ++p)
+#pragma unroll
+        for (int f = 0; f < NF; ++f) s_mr[p][f][e] = LD(a.f_src, p * S::N + f, gi);
+    }
   }
   __syncthreads();
   // phi (and for the own node j, the residual, phi^{t-1}) of region node r = (rx, ry, rz):
