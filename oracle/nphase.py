@@ -20,6 +20,9 @@ Sources of every step (paper sections / equations):
   m = rho u + m_phi, m_phi ..................... Sec. 2.2
   beta_pq, k_pq, g(phi), mu_phi_p, F_s ......... Sec. 2.2, free energy and Eq. (eq-Fs1)
   N-1 solved sets, D2Q9, natural M, diagonal S . Sec. 4 intro
+  half-way bounce-back walls (no-flux phase
+  field, no-slip flow) ......................... Sec. 4 intro
+  wetting condition and Young's relation ....... Sec. 4.2
 
 Readings where the paper is silent (each listed in the design notes of the repository):
   * the fluid relaxation time tau_g is local: from the mixed mu and rho at every node;
@@ -36,7 +39,13 @@ Readings where the paper is silent (each listed in the design notes of the repos
   * gravity acts as (rho - rho_bar) g with rho_bar the domain-mean density at t = 0;
   * rho_0 in lambda_0 is the constant RHO0 = 1;
   * initial state: f = f^eq(phi0, u=0), g = g^eq(P=0, u=0), u^{-1} = 0, phi^{-1} = phi0,
-    m_phi^{-1} = 0.
+    m_phi^{-1} = 0;
+  * walls (D2Q9 only): solid below y = 0 and above y = ny - 1, each wall half-way between
+    the last fluid row and a ghost row; x stays periodic.  The stencils read ghost values
+    there: phi_p from the one-sided wetting condition with the wall normal pointing out of
+    the fluid, phi_p(ghost) = phi_p(row) + (4/eps) sum_{q != p} phi_p phi_q cos theta_pq at
+    the adjacent fluid row; the Model B pair fractions are formed from the ghost phi; the
+    tensor m_phi u^- - u^- m_phi is odd across the wall (it vanishes there with u).
 """
 import numpy as np
 
@@ -56,7 +65,9 @@ class Config:
 
     cfg keys: lattice ('D2Q9'|'D3Q19'), nx, ny, nz, n_phases, sigma (N x N), rho (N),
     tau_g (N, per-phase fluid relaxation -> mu_p), mobility, eps, model ('A'|'B'),
-    model_a_n (integer >= 1), solve_all (bool), gravity (3 floats).
+    model_a_n (integer >= 1), solve_all (bool), gravity (3 floats), walls (bool: D2Q9
+    half-way bounce-back walls below y = 0 and above y = ny - 1, x periodic), contact_cos
+    (N-1 floats: cos theta_pN of each phase against the last one, Sec. 4.2).
     """
 
     def __init__(self, cfg):
@@ -82,6 +93,30 @@ class Config:
         self.mu = self.rho * (self.tau_g - 0.5) * CS2
         # solved phase-field sets: all N, or the first N-1 (Sec. 4 intro)
         self.NS = self.N if self.solve_all else self.N - 1
+        # walls normal to y (D2Q9) with the N-1 independent contact angles theta_pN
+        self.walls = bool(cfg.get("walls", False))
+        cos_pN = list(cfg.get("contact_cos", [0.0] * (self.N - 1)))
+        self.cos = young_cosines(self.sigma, cos_pN)
+        if self.walls:
+            assert d == 2 and self.ny >= 2, "walls: D2Q9 with ny >= 2"
+
+
+def young_cosines(sigma, cos_pN):
+    """Sec. 4.2: every pairwise contact angle from the N-1 independent ones theta_pN
+    (phase p against the last phase, measured on the side of p):
+    cos theta_pq = (sigma_pN cos theta_pN - sigma_qN cos theta_qN) / sigma_pq for p, q < N,
+    cos theta_Np = -cos theta_pN, and 0 on the diagonal."""
+    N = sigma.shape[0]
+    last = N - 1
+    c = np.zeros((N, N))
+    for p in range(N - 1):
+        c[p, last] = float(cos_pN[p])
+        c[last, p] = -float(cos_pN[p])
+    for p in range(N - 1):
+        for q in range(N - 1):
+            if p != q:
+                c[p, q] = (sigma[p, last] * c[p, last] - sigma[q, last] * c[q, last]) / sigma[p, q]
+    return c
 
 
 # ----------------------------------------------------------------------------------------
@@ -94,23 +129,64 @@ def shift(a, c):
                    axis=tuple(-1 - k for k in range(d)))
 
 
-def grad(chi, lat):
+def neighbour(chi, c, ghost=None):
+    """chi(x + c).  ghost = None: periodic.  Otherwise (2D walls normal to y) ghost =
+    (lo, hi), the rows that stand below y = 0 and above y = ny - 1; x stays periodic."""
+    if ghost is None:
+        return shift(chi, c)
+    lo, hi = ghost
+    ext = np.concatenate([lo[..., None, :], chi, hi[..., None, :]], axis=-2)
+    ext = np.roll(ext, -int(c[0]), axis=-1)
+    ny = chi.shape[-2]
+    cy = int(c[1])
+    return ext[..., 1 + cy:1 + cy + ny, :]
+
+
+def grad(chi, lat, ghost=None):
     """Isotropic central gradient: sum_{i != 0} w_i c_i chi(x + c_i) / c_s^2."""
     out = np.zeros((lat.d,) + chi.shape)
     for i in range(1, lat.Q):
-        s = shift(chi, lat.c[i])
+        s = neighbour(chi, lat.c[i], ghost)
         for a in range(lat.d):
             if lat.c[i, a] != 0:
                 out[a] += lat.w[i] * lat.c[i, a] * s / CS2
     return out
 
 
-def laplacian(chi, lat):
+def laplacian(chi, lat, ghost=None):
     """Isotropic Laplacian: sum_{i != 0} 2 w_i [chi(x + c_i) - chi(x)] / c_s^2."""
     out = np.zeros(chi.shape)
     for i in range(1, lat.Q):
-        out += 2.0 * lat.w[i] * (shift(chi, lat.c[i]) - chi) / CS2
+        out += 2.0 * lat.w[i] * (neighbour(chi, lat.c[i], ghost) - chi) / CS2
     return out
+
+
+def wetting_ghost(C, row):
+    """Ghost values of the N order parameters behind a wall from the adjacent fluid row
+    row [N, nx]: the wetting condition of Sec. 4.2, n_w . grad phi_p =
+    sum_{q != p} (4/eps) phi_p phi_q cos theta_pq with n_w pointing from the fluid into the
+    wall, taken one-sided across the half-way wall (one lattice spacing, phi_p phi_q at the
+    fluid row)."""
+    N = row.shape[0]
+    out = np.empty_like(row)
+    for p in range(N):
+        acc = np.zeros(row.shape[1:])
+        for q in range(N):
+            if q != p:
+                acc = acc + C.cos[p, q] * row[p] * row[q]
+        out[p] = row[p] + (4.0 / C.eps) * acc
+    return out
+
+
+def phi_ghosts(C, phi):
+    """(lo, hi) ghost rows of all N phases, or None without walls."""
+    if not C.walls:
+        return None
+    return wetting_ghost(C, phi[:, 0, :]), wetting_ghost(C, phi[:, -1, :])
+
+
+def _pick(ghost, p):
+    return None if ghost is None else (ghost[0][p], ghost[1][p])
 
 
 def _dot(a, b):
@@ -160,7 +236,14 @@ def source_model_a(phi, G, C):
     return R
 
 
-def source_model_b(phi, C):
+def pair_fraction(a, b):
+    """phi_pq = phi_p / (phi_p + phi_q), 1/2 where both vanish."""
+    s = a + b
+    ok = s > PAIR_EPS
+    return np.where(ok, a / np.where(ok, s, 1.0), 0.5)
+
+
+def source_model_b(phi, C, ghost=None):
     """Eq. (eq-source2): R_p = sum_{q != p} 4 phi_p phi_q / eps * n_pq with
     n_pq = grad(phi_pq)/|grad(phi_pq)| and phi_pq = phi_p / (phi_p + phi_q)."""
     lat = C.lat
@@ -168,10 +251,12 @@ def source_model_b(phi, C):
     R = np.zeros((N, lat.d) + phi.shape[1:])
     for p in range(N):
         for q in range(p + 1, N):
-            s = phi[p] + phi[q]
-            ok = s > PAIR_EPS
-            phi_pq = np.where(ok, phi[p] / np.where(ok, s, 1.0), 0.5)
-            n_pq = _normalize(grad(phi_pq, lat))
+            phi_pq = pair_fraction(phi[p], phi[q])
+            gpq = None
+            if ghost is not None:
+                gpq = (pair_fraction(ghost[0][p], ghost[0][q]),
+                       pair_fraction(ghost[1][p], ghost[1][q]))
+            n_pq = _normalize(grad(phi_pq, lat, gpq))
             coef = 4.0 * phi[p] * phi[q] / C.eps
             R[p] = R[p] + coef * n_pq
             R[q] = R[q] + coef * (-n_pq)
@@ -259,9 +344,10 @@ def macroscopic(C, state):
         mu = mu + C.mu[p] * phi[p]
     tau_g = 0.5 + mu / (rho * CS2)
 
-    # stencils
-    G = np.stack([grad(phi[p], lat) for p in range(C.N)])
-    L = np.stack([laplacian(phi[p], lat) for p in range(C.N)])
+    # stencils (with walls: ghost rows from the wetting condition)
+    gh = phi_ghosts(C, phi)
+    G = np.stack([grad(phi[p], lat, _pick(gh, p)) for p in range(C.N)])
+    L = np.stack([laplacian(phi[p], lat, _pick(gh, p)) for p in range(C.N)])
     grad_rho = C.rho[0] * G[0]
     for p in range(1, C.N):
         grad_rho = grad_rho + C.rho[p] * G[p]
@@ -270,7 +356,7 @@ def macroscopic(C, state):
     if C.model == "A":
         R = source_model_a(phi, G, C)
     else:
-        R = source_model_b(phi, C)
+        R = source_model_b(phi, C, gh)
 
     # chemical potentials and the potential-form surface tension
     gp = [gprime(phi[p]) for p in range(C.N)]
@@ -300,7 +386,8 @@ def macroscopic(C, state):
     for b in range(d):
         for a in range(d):
             A_ab = m_phi[a] * u_prev[b] - u_prev[a] * m_phi[b]
-            Fc[b] = Fc[b] - 0.5 * grad(A_ab, lat)[a]
+            ga = None if gh is None else (-A_ab[0], -A_ab[-1])
+            Fc[b] = Fc[b] - 0.5 * grad(A_ab, lat, ga)[a]
     Fg = (rho - state["rho_bar"])[None] * C.gravity.reshape((d,) + (1,) * d)
     F = Fs + Fg + Fc
 
@@ -430,6 +517,12 @@ def flow_collision(C, g, mac, u_prev, mphi_prev):
     return np.tensordot(Minv, mstar, axes=(1, 0)), dict(geq=geq, Fi=Fi, M2F=M2F)
 
 
+def opposite(lat):
+    """Index of -c_i for every direction i."""
+    return np.array([int(np.flatnonzero((lat.c == -lat.c[i]).all(axis=1))[0])
+                     for i in range(lat.Q)])
+
+
 def step(C, state, nsteps=1):
     """Advance the state by nsteps time steps (returns a new state dict)."""
     for _ in range(nsteps):
@@ -453,6 +546,15 @@ def _one_step(C, state):
         ci = lat.c[i]
         fnew[:, i] = shift(fstar[:, i], -ci)
         gnew[i] = shift(gstar[i], -ci)
+    if C.walls:
+        # half-way bounce-back (Sec. 4 intro): a population that would arrive from behind a
+        # wall is the node's own post-collision population of the opposite direction
+        opp = opposite(lat)
+        for i in range(lat.Q):
+            row = {1: 0, -1: C.ny - 1}.get(int(lat.c[i, 1]))
+            if row is not None:
+                fnew[:, i, row, :] = fstar[:, opp[i], row, :]
+                gnew[i, row, :] = gstar[opp[i], row, :]
     return {
         "f": fnew, "g": gnew,
         "u_prev": u.copy(),

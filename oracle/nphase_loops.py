@@ -19,7 +19,12 @@ velocity and Euler time derivatives (Sec. 3 closing paragraph); N-1 evolved sets
 M, diagonal S (Sec. 4 intro).  Readings where the paper is silent are the same as the
 vectorised oracle's (local tau_g, normal and pair-fraction guards, n_qp = -n_pq, the
 reconstructed phase treated as a field, first-index divergence, (rho - rho_bar) g,
-rho_0 = 1).
+rho_0 = 1).  Walls (D2Q9): solid below y = 0 and above y = ny - 1 with half-way
+bounce-back (Sec. 4 intro); the stencils read ghost nodes behind a wall, whose order
+parameters follow from the wetting condition of Sec. 4.2 at the adjacent fluid node (wall
+normal out of the fluid, one lattice spacing, contact angles from the Sec. 4.2 Young
+relation), pair fractions from those, and the tensor m_phi u^- - u^- m_phi with its sign
+flipped (the same readings as the vectorised oracle).
 """
 import itertools
 import math
@@ -57,13 +62,38 @@ class Params:
         grav = list(cfg.get("gravity", [0.0, 0.0, 0.0]))
         self.grav = [float(grav[a]) for a in range(self.d)]
         self.nodes = list(itertools.product(*[range(n) for n in self.shape]))
+        self.walls = bool(cfg.get("walls", False))
+        # contact angles: theta_pN given (p < N), Young's relation for the other pairs
+        cN = [float(v) for v in cfg.get("contact_cos", [0.0] * (self.N - 1))]
+        last = self.N - 1
+        self.cos = [[0.0] * self.N for _ in range(self.N)]
+        for p in range(self.N):
+            for q in range(self.N):
+                if p == q:
+                    continue
+                if q == last:
+                    self.cos[p][q] = cN[p]
+                elif p == last:
+                    self.cos[p][q] = -cN[q]
+                else:
+                    self.cos[p][q] = (sig[p, last] * cN[p] - sig[q, last] * cN[q]) / sig[p, q]
+
+    def ghost(self, Y):
+        """True for a node behind a wall (2D: row -1 or ny)."""
+        return self.walls and not (0 <= Y[0] < self.shape[0])
+
+    def facing(self, Y):
+        """The fluid node in front of the ghost node Y."""
+        return (0 if Y[0] < 0 else self.shape[0] - 1, Y[1])
 
     def nbr(self, X, c):
-        """Array index of the node X + c (c in (x, y[, z]) order), periodic."""
+        """Array index of the node X + c (c in (x, y[, z]) order), periodic; with walls the
+        row is not wrapped, so a node behind a wall comes back as row -1 or ny."""
         if self.d == 2:
             y, x = X
             ny, nx = self.shape
-            return ((y + int(c[1])) % ny, (x + int(c[0])) % nx)
+            yy = y + int(c[1]) if self.walls else (y + int(c[1])) % ny
+            return (yy, (x + int(c[0])) % nx)
         z, y, x = X
         nz, ny, nx = self.shape
         return ((z + int(c[2])) % nz, (y + int(c[1])) % ny, (x + int(c[0])) % nx)
@@ -102,6 +132,13 @@ def _lap_at(P, X, value):
     return out
 
 
+def _opp(lat, i):
+    for j in range(lat.Q):
+        if all(lat.c[j, a] == -lat.c[i, a] for a in range(lat.d)):
+            return j
+    raise ValueError(i)
+
+
 def step(cfg, state, nsteps=1):
     P = Params(cfg)
     for _ in range(nsteps):
@@ -128,11 +165,20 @@ def _one_step(P, st):
             ph.append(1.0 - sum(ph))
         phim[X] = ph
 
+    def phi_g(Y):
+        """Order parameters at a node or, behind a wall, from the wetting condition."""
+        if not P.ghost(Y):
+            return phi[Y]
+        ph = phi[P.facing(Y)]
+        return [ph[p] + 4.0 / P.eps * sum(P.cos[p][q] * ph[p] * ph[q]
+                                           for q in range(N) if q != p)
+                for p in range(N)]
+
     # stencils, sources, chemical potentials, fluxes (node by node)
     G, Lap, R, mphi = {}, {}, {}, {}
     for X in P.nodes:
-        G[X] = [_grad_at(P, X, lambda Y, p=p: phi[Y][p]) for p in range(N)]
-        Lap[X] = [_lap_at(P, X, lambda Y, p=p: phi[Y][p]) for p in range(N)]
+        G[X] = [_grad_at(P, X, lambda Y, p=p: phi_g(Y)[p]) for p in range(N)]
+        Lap[X] = [_lap_at(P, X, lambda Y, p=p: phi_g(Y)[p]) for p in range(N)]
     for X in P.nodes:
         ph = phi[X]
         Rp = [[0.0] * d for _ in range(N)]
@@ -149,8 +195,9 @@ def _one_step(P, st):
             for p in range(N):
                 for q in range(p + 1, N):
                     def frac(Y, p=p, q=q):
-                        s_ = phi[Y][p] + phi[Y][q]
-                        return phi[Y][p] / s_ if s_ > PAIR_EPS else 0.5
+                        v = phi_g(Y)
+                        s_ = v[p] + v[q]
+                        return v[p] / s_ if s_ > PAIR_EPS else 0.5
                     npq = _normalized(_grad_at(P, X, frac))
                     coef = 4.0 * ph[p] * ph[q] / P.eps
                     for a in range(d):
@@ -180,10 +227,15 @@ def _one_step(P, st):
                 Fs[a] += m_p * G[X][p][a]
         # correction force from the tensor m_phi u^- - u^- m_phi (first-index divergence)
         up_at = lambda Y, a: st["u_prev"][(a,) + Y]
+
+        def tensor(Y, a, b):
+            if P.ghost(Y):
+                return -tensor(P.facing(Y), a, b)
+            return mphi[Y][a] * up_at(Y, b) - up_at(Y, a) * mphi[Y][b]
         Fc = [0.0] * d
         for b in range(d):
             for a in range(d):
-                Aab = lambda Y, a=a, b=b: mphi[Y][a] * up_at(Y, b) - up_at(Y, a) * mphi[Y][b]
+                Aab = lambda Y, a=a, b=b: tensor(Y, a, b)
                 Fc[b] -= 0.5 * _grad_at(P, X, Aab)[a]
         F = [Fs[a] + (rho - rho_bar) * P.grav[a] + Fc[a] for a in range(d)]
         gx = [g[(i,) + X] for i in range(Q)]
@@ -217,7 +269,11 @@ def _one_step(P, st):
             Lf = Minv @ S_f @ M
             fs = fv - Lf @ (fv - feq) + (np.eye(Q) - 0.5 * Lf) @ Ri
             for i in range(Q):
-                new["f"][(p, i) + P.nbr(X, lat.c[i])] = fs[i]
+                Y = P.nbr(X, lat.c[i])
+                if P.ghost(Y):   # half-way bounce-back: back to X, opposite direction
+                    new["f"][(p, _opp(lat, i)) + X] = fs[i]
+                else:
+                    new["f"][(p, i) + Y] = fs[i]
 
         # flow collision (s2 = 1/tau_g on the second-order rows)
         M2F = [[u[a] * F[b] + F[a] * u[b]
@@ -246,7 +302,11 @@ def _one_step(P, st):
         Lg = Minv @ S_g @ M
         gs = np.array(gx) - Lg @ (np.array(gx) - geq) + (np.eye(Q) - 0.5 * Lg) @ Fi
         for i in range(Q):
-            new["g"][(i,) + P.nbr(X, lat.c[i])] = gs[i]
+            Y = P.nbr(X, lat.c[i])
+            if P.ghost(Y):
+                new["g"][(_opp(lat, i),) + X] = gs[i]
+            else:
+                new["g"][(i,) + Y] = gs[i]
         for a in range(d):
             new["u_prev"][(a,) + X] = u[a]
             new["mphi_prev"][(a,) + X] = mp[a]

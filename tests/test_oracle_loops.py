@@ -51,10 +51,35 @@ def test_loops_match_vectorised(lattice, dims, model, n_exp, solve_all, grav):
                           tau_g=[0.8, 0.6, 1.1], mobility=0.03, eps=3.0, model=model,
                           model_a_n=n_exp, solve_all=solve_all, gravity=grav)
     st = _state(cfg, seed=len(lattice) + nx + 3 * ny + 7 * nz)
+    _compare(cfg, st, f"{lattice} {model}")
+
+
+def _compare(cfg, st, tag):
     a = O.step(O.Config(cfg), st, 3)
     b = OL.step(cfg, st, 3)
     for k in ("f", "g", "u_prev", "phi_prev", "mphi_prev"):
         scale = max(np.abs(a[k]).max(), 1e-300)
         err = np.abs(a[k] - b[k]).max() / scale
-        print(f"  {lattice} {model} {k}: {err:.2e}")
+        print(f"  {tag} {k}: {err:.2e}")
         assert err <= 1e-12, k
+
+
+WALL_CASES = [
+    ("B", 1, False, (0.0, -1e-3, 0.0), (0.4, -0.3)),
+    ("A", 2, True, (1e-3, 0.0, 0.0), (-0.6, 0.2)),
+    ("B", 1, True, (0.0, 0.0, 0.0), (0.0, 0.0)),
+]
+
+
+@pytest.mark.parametrize("model,n_exp,solve_all,grav,cos_pN", WALL_CASES)
+def test_loops_match_vectorised_walls(model, n_exp, solve_all, grav, cos_pN):
+    """Walls below y = 0 and above y = ny - 1 (half-way bounce-back, wetting ghosts)."""
+    N = 3
+    sigma = inputs.random_sigma(N, np.random.default_rng(12), 0.005, 0.02)
+    cfg = inputs.base_cfg("D2Q9", 6, 5, 1, N, sigma, rho=[1.0, 2.5, 0.7],
+                          tau_g=[0.8, 0.6, 1.1], mobility=0.03, eps=3.0, model=model,
+                          model_a_n=n_exp, solve_all=solve_all, gravity=grav)
+    cfg["walls"] = True
+    cfg["contact_cos"] = list(cos_pN)
+    st = _state(cfg, seed=29 + n_exp)
+    _compare(cfg, st, f"walls {model}")
