@@ -14,7 +14,10 @@
  *   - isotropic lattice-weight gradient/Laplacian stencils, lagged velocity in the force
  *     and explicit Euler time derivatives (Sec. 3 closing paragraph).
  * Lattices: D2Q9 (the paper's) and D3Q19 (raw-moment basis built the same way).
- * Boundaries: periodic in every direction.
+ * Boundaries: periodic in every direction, or (D2Q9) solid walls below y = 0 and above
+ * y = ny - 1 with x periodic: half-way bounce-back for the no-flux phase field and the
+ * no-slip flow (Sec. 4 intro) and the N-phase wetting condition with Young's relation
+ * (Sec. 4.2).
  *
  * Conventions
  *   - Every function returns an int status: NPHASE_OK (0) or a negative error code.
@@ -85,6 +88,22 @@ typedef struct {
   double mobility;       /* M > 0; phase-field relaxation tau_f = 1/2 + M / c_s^2 (Sec. 3) */
   double eps;            /* interface thickness epsilon > 0 (Sec. 2.1)                     */
   double gravity[3];     /* body force (rho - rho_bar) g, rho_bar = mean density at t = 0 */
+  int32_t walls;         /* 0: periodic.  1 (D2Q9 only, ny >= 2): walls half-way below row 0
+                            and above row ny - 1.  Populations that would stream in from a
+                            wall are the node's own post-collision populations of the
+                            opposite direction.  The gradient and Laplacian stencils read a
+                            ghost row behind each wall: phi_p(ghost) = phi_p + (4/eps)
+                            sum_{q != p} phi_p phi_q cos theta_pq at the adjacent fluid node
+                            (the wetting condition n_w . grad phi_p = (4/eps) sum phi_p phi_q
+                            cos theta_pq with n_w pointing into the wall, one-sided), Model B
+                            pair fractions from those values, and m_phi u - u m_phi with
+                            its sign flipped (it vanishes at the wall with u).           */
+  int32_t pad0;
+  double contact_cos[NPHASE_MAX_N]; /* with walls: cos theta_pN, p = 0..N-2, the contact
+                            angle of phase p against the last phase, measured in phase p, in
+                            [-1, 1]; every other pair follows Young's relation
+                            cos theta_pq = (sigma_pN cos theta_pN - sigma_qN cos theta_qN) /
+                            sigma_pq (Sec. 4.2).  Ignored without walls.                  */
 } nphase_lbm_params;
 
 /* Bytes of device workspace for this parameter set: both state buffers, the reduction
@@ -98,7 +117,8 @@ int nphase_lbm_workspace_bytes(const nphase_lbm_params *params, size_t *bytes_ho
 
 /* Validate and copy the parameters, carve the caller's workspace and bind the stream.
  * Errors: EINVAL (bad parameters, NULL pointers, misaligned workspace), ENOMEM
- * (ws_bytes too small), ENOTSUP (N outside 2..6).  No device work is done. */
+ * (ws_bytes too small), ENOTSUP (N outside 2..6, walls on D3Q19).  No device work is
+ * done. */
 int nphase_lbm_create(const nphase_lbm_params *params, void *workspace_dev, size_t ws_bytes,
                       void *hip_stream, nphase_lbm_t *out_host);
 
@@ -162,7 +182,8 @@ int nphase_lbm_save_state64(nphase_lbm_t h, void *state64_dev);
  * step evaluated along the FP32 trajectory.  Guarded points of the forward (normals below
  * the guard, pair fractions of absent pairs) are differentiated as the constants the
  * forward returns there.  The gravity reference density is treated as fixed, so these
- * entry points return NPHASE_ENOTSUP for non-zero gravity.
+ * entry points return NPHASE_ENOTSUP for non-zero gravity; they also return it for walls
+ * (the reverse of the wall step is not built).
  *
  * adjoint_workspace_bytes: device scratch for one adjoint step (caller-owned).
  * adjoint_seed:  adj_state = dL/ds^T for L depending on the phase fields phi(T) [N][V]

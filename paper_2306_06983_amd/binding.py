@@ -40,6 +40,9 @@ class Params(ctypes.Structure):
         ("mobility", ctypes.c_double),
         ("eps", ctypes.c_double),
         ("gravity", ctypes.c_double * 3),
+        ("walls", ctypes.c_int32),
+        ("pad0", ctypes.c_int32),
+        ("contact_cos", ctypes.c_double * MAX_N),
     ]
 
 
@@ -125,6 +128,9 @@ def make_params(cfg, precision="fp64"):
     g = list(cfg.get("gravity", [0.0, 0.0, 0.0])) + [0.0, 0.0, 0.0]
     for d in range(3):
         p.gravity[d] = float(g[d])
+    p.walls = 1 if cfg.get("walls", False) else 0
+    for i, c in enumerate(cfg.get("contact_cos", [])):
+        p.contact_cos[i] = float(c)
     return p
 
 

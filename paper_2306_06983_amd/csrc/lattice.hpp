@@ -50,4 +50,13 @@ __host__ __device__ constexpr int cnorm2(int i) {
   return L::c(i, 0) * L::c(i, 0) + L::c(i, 1) * L::c(i, 1) + L::c(i, 2) * L::c(i, 2);
 }
 
+// index of -c_i
+template <class L>
+__host__ __device__ constexpr int opposite(int i) {
+  for (int j = 0; j < L::Q; ++j)
+    if (L::c(j, 0) == -L::c(i, 0) && L::c(j, 1) == -L::c(i, 1) && L::c(j, 2) == -L::c(i, 2))
+      return j;
+  return -1;
+}
+
 }  // namespace nphase

@@ -117,8 +117,19 @@ int validate(const nphase_lbm_params* p, std::string* why) {
   if (!(p->eps > 0.0) || !std::isfinite(p->eps)) return bad("eps must be > 0");
   for (int d = 0; d < 3; ++d)
     if (!std::isfinite(p->gravity[d])) return bad("gravity not finite");
+  if (p->walls != 0 && p->walls != 1) return bad("walls must be 0 or 1");
+  if (p->walls) {
+    if (p->ny < 2) return bad("walls need ny >= 2");
+    for (int i = 0; i + 1 < N; ++i)
+      if (!(p->contact_cos[i] >= -1.0 && p->contact_cos[i] <= 1.0))
+        return bad("contact_cos must lie in [-1, 1]");
+  }
   if (N < NMIN || N > NMAX) {
     if (why) *why = "n_phases outside the instantiated range [2, 6]";
+    return NPHASE_ENOTSUP;
+  }
+  if (p->walls && p->lattice != NPHASE_D2Q9) {
+    if (why) *why = "walls are built for D2Q9 only";
     return NPHASE_ENOTSUP;
   }
   return NPHASE_OK;
@@ -177,6 +188,23 @@ void fill_args(nphase_lbm_t h, StepArgs<T>* out) {
     a.four_over_eps = (T)(4.0 / p.eps);
     a.rho_bar = (T)h->rho_bar;
     for (int d = 0; d < 3; ++d) a.grav[d] = (T)p.gravity[d];
+    a.walls = p.walls;
+    // wetting: (4/eps) cos theta_pq per pair p < q; cos theta_pN given, the other pairs
+    // from Young's relation (Sec. 4.2); cos theta_qp = -cos theta_pq
+    const int last = h->N - 1;
+    for (int i = 0, k = 0; i < h->N; ++i) {
+      for (int j = i + 1; j < h->N; ++j, ++k) {
+        double c;
+        if (j == last) {
+          c = p.contact_cos[i];
+        } else {
+          const double s_iN = p.sigma[i * NPHASE_MAX_N + last];
+          const double s_jN = p.sigma[j * NPHASE_MAX_N + last];
+          c = (s_iN * p.contact_cos[i] - s_jN * p.contact_cos[j]) / p.sigma[i * NPHASE_MAX_N + j];
+        }
+        a.wet[k] = p.walls ? (T)(4.0 / p.eps * c) : T(0);
+      }
+    }
   }
 }
 
@@ -608,6 +636,10 @@ int adj_check(nphase_lbm_t h) {
     h->err = "the adjoint treats the gravity reference density as fixed: needs gravity = 0";
     return NPHASE_ENOTSUP;
   }
+  if (h->prm.walls) {
+    h->err = "the adjoint is built for periodic boundaries only";
+    return NPHASE_ENOTSUP;
+  }
   return NPHASE_OK;
 }
 
@@ -713,19 +745,19 @@ int nphase_lbm_save_state64(nphase_lbm_t h, void* state_dev) {
     const double *u = (const double*)h->u[c], *mm = (const double*)h->mm;
     if (h->lat == NPHASE_D2Q9)
       hipLaunchKernelGGL((mr_to_pop64_kernel<double, LAT_D2Q9>), dim3(nb), dim3(256), 0, h->stream,
-                         f, g, u, mm, o.f, o.g, o.u, o.pm, o.mm, h->NS, p.nx, p.ny, p.nz, first);
+                         f, g, u, mm, o.f, o.g, o.u, o.pm, o.mm, h->NS, p.nx, p.ny, p.nz, first, p.walls);
     else
       hipLaunchKernelGGL((mr_to_pop64_kernel<double, LAT_D3Q19>), dim3(nb), dim3(256), 0, h->stream,
-                         f, g, u, mm, o.f, o.g, o.u, o.pm, o.mm, h->NS, p.nx, p.ny, p.nz, first);
+                         f, g, u, mm, o.f, o.g, o.u, o.pm, o.mm, h->NS, p.nx, p.ny, p.nz, first, p.walls);
   } else {
     const float *f = (const float*)h->f[c], *g = (const float*)h->g[c];
     const float *u = (const float*)h->u[c], *mm = (const float*)h->mm;
     if (h->lat == NPHASE_D2Q9)
       hipLaunchKernelGGL((mr_to_pop64_kernel<float, LAT_D2Q9>), dim3(nb), dim3(256), 0, h->stream,
-                         f, g, u, mm, o.f, o.g, o.u, o.pm, o.mm, h->NS, p.nx, p.ny, p.nz, first);
+                         f, g, u, mm, o.f, o.g, o.u, o.pm, o.mm, h->NS, p.nx, p.ny, p.nz, first, p.walls);
     else
       hipLaunchKernelGGL((mr_to_pop64_kernel<float, LAT_D3Q19>), dim3(nb), dim3(256), 0, h->stream,
-                         f, g, u, mm, o.f, o.g, o.u, o.pm, o.mm, h->NS, p.nx, p.ny, p.nz, first);
+                         f, g, u, mm, o.f, o.g, o.u, o.pm, o.mm, h->NS, p.nx, p.ny, p.nz, first, p.walls);
   }
   HIPCHK(hipGetLastError(), "save state64");
   return NPHASE_OK;

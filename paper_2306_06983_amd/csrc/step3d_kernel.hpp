@@ -790,7 +790,7 @@ __global__ void __launch_bounds__(256)
     mr_to_pop64_kernel(const T* __restrict__ mr, const T* __restrict__ g, const T* __restrict__ u,
                        const T* __restrict__ mm, double* __restrict__ f64, double* __restrict__ g64,
                        double* __restrict__ u64, double* __restrict__ pm64, double* __restrict__ mm64,
-                       int NS, int nx, int ny, int nz, int first) {
+                       int NS, int nx, int ny, int nz, int first, int walls) {
   using L = Lattice<LAT>;
   constexpr int D = L::D, Q = L::Q;
   using S = MR<T, D>;
@@ -811,11 +811,15 @@ __global__ void __launch_bounds__(256)
       } else {
         const int xs = (x - L::c(i, 0) + nx) % nx, ys = (y - L::c(i, 1) + ny) % ny;
         const int zs = (z - L::c(i, 2) + nz) % nz;
-        const long long sn = xs + (long long)nx * (ys + (long long)ny * zs);
+        // behind a wall (rows -1 and ny): half-way bounce-back, the node's own population
+        // of the opposite direction
+        const bool bb = walls && (y - L::c(i, 1) < 0 || y - L::c(i, 1) >= ny);
+        const long long sn = bb ? gl : xs + (long long)nx * (ys + (long long)ny * zs);
+        const double sg = bb ? -1.0 : 1.0;
         double cA = 0.0, cD = 0.0;
         for (int d = 0; d < D; ++d) {
-          cA += L::c(i, d) * at(p, S::A + d, sn);
-          cD += L::c(i, d) * at(p, S::DD + d, sn);
+          cA += sg * L::c(i, d) * at(p, S::A + d, sn);
+          cD += sg * L::c(i, d) * at(p, S::DD + d, sn);
         }
         v = L::w(i) * (at(p, S::PHI, sn) + cA);
         if (cnorm2<L>(i) == 1) v += 0.5 * cD;

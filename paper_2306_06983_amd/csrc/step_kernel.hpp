@@ -28,9 +28,18 @@
 //   u [D][V]       velocity u^{t-1} (ping-pong: read at radius 1).
 //   pm [NS][V]     phi^{t-1} of the evolved sets (ping-pong: FP32 reads it at radius 2).
 //   mm [D][V]      m_phi^{t-1} (read and written at the own node only: in place).
+//
+// Walls (D2Q9, below row 0 and above row ny - 1, half-way): a population that would be
+// pulled or pushed across a wall is the node's own post-collision population of the
+// opposite direction (bounce-back, Sec. 4 intro); the stencils read a ghost row behind the
+// wall holding phi from the wetting condition of Sec. 4.2 (one-sided, at the adjacent fluid
+// row), the pair fractions of those values and the tensor m_phi u - u m_phi with its sign
+// flipped.  Only tiles whose halo reaches row 0 or ny - 1 take these branches.
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "lattice.hpp"
 
@@ -74,6 +83,9 @@ struct StepArgs {
   T four_over_eps;        // 4 / eps
   T rho_bar;
   T grav[3];
+  int walls;   // D2Q9: 1 = walls half-way below row 0 and above row ny - 1 (x periodic)
+  // per unordered pair p < q: (4 / eps) cos theta_pq (cos theta_qp = -cos theta_pq)
+  T wet[MAXN * (MAXN - 1) / 2];
 };
 
 template <int LAT>
@@ -237,6 +249,8 @@ __global__ void __launch_bounds__(TileShape<LAT>::NT) nphase_step_kernel(const S
   const int tx0 = (tile % a.ntx) * TX;
   const int ty0 = ((tile / a.ntx) % a.nty) * TY;
   const int tz0 = (tile / (a.ntx * a.nty)) * TZ;
+  // the halo (rows ty0 - 2 .. ty0 + TY + 1) reaches row 0 or row ny - 1 of a walled box
+  const bool wall_tile = (D == 2) && a.walls && (ty0 <= 2 || ty0 + TY + 2 >= ny);
 
   // Element (component, node) of a [component][V] array as a uniform stream base plus a
   // 32-bit node offset (the host checks V < 2^32): one offset register per node serves
@@ -292,8 +306,11 @@ __global__ void __launch_bounds__(TileShape<LAT>::NT) nphase_step_kernel(const S
   // phi (and for the own node j, the residual, phi^{t-1}) of region node r = (rx, ry, rz):
   // the pulled populations f_i = f*_i(x - c_i) rebuilt from the moment form of the
   // upwind neighbours (at t = 0 the initial equilibrium: phi = phi0, j = 0)
-  auto stage1 = [&](int r, int rx, int ry, int rz, long long gi, bool own) {
+  auto stage1 = [&](auto wall, int r, int rx, int ry, int rz, long long gi,
+                    bool own) __attribute__((always_inline)) {
+    constexpr bool W = decltype(wall)::value;
     const int e = (rx + 1) + EX * ((ry + 1) + EY * (D == 3 ? rz + 1 : 0));
+    const int gyr = ty0 - 2 + ry;   // row of the node (not wrapped)
 #pragma unroll
     for (int p = 0; p < NS; ++p) {
       const T ph_own = s_mr[p][S::PHI][e];
@@ -313,13 +330,20 @@ __global__ void __launch_bounds__(TileShape<LAT>::NT) nphase_step_kernel(const S
             if constexpr (DEV) fi = res;   // the rest population carries the residual
             else fi = T(L::w(0)) * ph_own;
           } else {
-            const int es = e - L::c(i, 0) - EX * (L::c(i, 1) + EY * L::c(i, 2));
+            int es = e - L::c(i, 0) - EX * (L::c(i, 1) + EY * L::c(i, 2));
+            // behind a wall: bounce-back, f_i = f*_{-i} of the node itself
+            bool bb = false;
+            if constexpr (W) {
+              bb = gyr - L::c(i, 1) < 0 || gyr - L::c(i, 1) >= ny;
+              if (bb) es = e;
+            }
             T cA = T(0), cD = T(0);
 #pragma unroll
             for (int d = 0; d < D; ++d) {
               if (L::c(i, d) == 1) cA += s_mr[p][S::A + d][es];
               if (L::c(i, d) == -1) cA -= s_mr[p][S::A + d][es];
             }
+            if (bb) cA = -cA;
             const T phs = s_mr[p][S::PHI][es];
             // FP32: deviation from the rest weights of the node's own phi^{t-1}
             if constexpr (DEV) fi = T(L::w(i)) * ((phs - ph_own) + cA);
@@ -330,6 +354,7 @@ __global__ void __launch_bounds__(TileShape<LAT>::NT) nphase_step_kernel(const S
                 if (L::c(i, d) == 1) cD += s_mr[p][S::DD + d][es];
                 if (L::c(i, d) == -1) cD -= s_mr[p][S::DD + d][es];
               }
+              if (bb) cD = -cD;
               fi += T(0.5) * cD;
             }
           }
@@ -361,17 +386,58 @@ __global__ void __launch_bounds__(TileShape<LAT>::NT) nphase_step_kernel(const S
       }
     }
   };
-  stage1(r_own, lx + 2, ly + 2, lz + HZ, g_own, true);
-  {
+  auto stage1_all = [&](auto wall) __attribute__((always_inline)) {
+    stage1(wall, r_own, lx + 2, ly + 2, lz + HZ, g_own, true);
     constexpr int NRING = NR - NTH;
     for (int k = t; k < NRING; k += NTH) {
       int rx, ry, rz;
       ring_coord<2, RX, RY, RZ>(k, rx, ry, rz);
-      stage1(rx + RX * (ry + RY * rz), rx, ry, rz, DEV ? region_gidx(rx, ry, rz) : 0, false);
+      stage1(wall, rx + RX * (ry + RY * rz), rx, ry, rz, DEV ? region_gidx(rx, ry, rz) : 0,
+             false);
     }
-  }
+  };
+  if (wall_tile) stage1_all(std::true_type{});
+  else stage1_all(std::false_type{});
   // the moment form is dead from here on: its space takes the pair fractions and tensor
   __syncthreads();
+  if constexpr (D == 2) {
+    if (wall_tile) {
+      // ghost rows -1 and ny: phi_p + sum_{q != p} (4/eps) cos theta_pq phi_p phi_q of the
+      // adjacent fluid row (the wetting condition, one-sided across the half-way wall)
+      for (int k = t; k < 2 * RX; k += NTH) {
+        const int rx = k % RX;
+        const int gyg = k < RX ? -1 : ny;
+        const int ry = gyg - ty0 + 2;
+        if (ry < 0 || ry >= RY) continue;
+        const int rf = rx + RX * (ry + (gyg < 0 ? 1 : -1));
+        T ph[N];
+#pragma unroll
+        for (int p = 0; p < NS; ++p) ph[p] = s_phi[p][rf];
+        if constexpr (!SA) {
+          T rest = ph[0];
+#pragma unroll
+          for (int p = 1; p < NS; ++p) rest += ph[p];
+          ph[N - 1] = T(1) - rest;
+        }
+        T acc[N];
+#pragma unroll
+        for (int p = 0; p < N; ++p) acc[p] = T(0);
+        int kk = 0;
+#pragma unroll
+        for (int p = 0; p < N; ++p) {
+#pragma unroll
+          for (int q = p + 1; q < N; ++q, ++kk) {
+            const T v = a.wet[kk] * ph[p] * ph[q];
+            acc[p] += v;
+            acc[q] -= v;
+          }
+        }
+#pragma unroll
+        for (int p = 0; p < NS; ++p) s_phi[p][rx + RX * ry] = ph[p] + acc[p];
+      }
+      __syncthreads();
+    }
+  }
   if constexpr (PF_LDS) {
     for (int r = t; r < NR; r += NTH) {
       T ph[N];
@@ -523,14 +589,15 @@ __global__ void __launch_bounds__(TileShape<LAT>::NT) nphase_step_kernel(const S
     }
   };
   // antisymmetric tensor A_ab = m_a u^-_b - u^-_a m_b: components (xy) or (xy, xz, yz)
-  auto store_w = [&](int iq, long long gi) {
+  // (sg = -1: the value of a ghost node behind a wall, from the fluid node facing it)
+  auto store_w = [&](int iq, long long gi, T sg) {
     T um[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) um[d] = LD(a.u_src, d, (unsigned)gi);
-    s_w[0][iq] = mphi[0] * um[1] - um[0] * mphi[1];
+    s_w[0][iq] = sg * (mphi[0] * um[1] - um[0] * mphi[1]);
     if constexpr (D == 3) {
-      s_w[1][iq] = mphi[0] * um[2] - um[0] * mphi[2];
-      s_w[2][iq] = mphi[1] * um[2] - um[1] * mphi[2];
+      s_w[1][iq] = sg * (mphi[0] * um[2] - um[0] * mphi[2]);
+      s_w[2][iq] = sg * (mphi[1] * um[2] - um[1] * mphi[2]);
     }
   };
   {
@@ -539,14 +606,26 @@ __global__ void __launch_bounds__(TileShape<LAT>::NT) nphase_step_kernel(const S
       int ix, iy, iz;
       ring_coord<1, IX, IY, IZ>(k, ix, iy, iz);
       const int rz = (D == 3) ? iz + 1 : 0;
-      const int r = (ix + 1) + RX * ((iy + 1) + RY * rz);
-      stage2(r, false);
-      store_w(ix + IX * (iy + IY * iz), region_gidx(ix + 1, iy + 1, rz));
+      int ry = iy + 1;
+      T sg = T(1);
+      if (wall_tile) {   // ghost rows take the odd reflection of the facing fluid node
+        const int gy = ty0 - 1 + iy;
+        if (gy < 0) { ++ry; sg = T(-1); }
+        else if (gy >= ny) { --ry; sg = T(-1); }
+      }
+      stage2((ix + 1) + RX * (ry + RY * rz), false);
+      store_w(ix + IX * (iy + IY * iz), region_gidx(ix + 1, ry, rz), sg);
     }
   }
-  // own node last so that G, L, R, m_phi stay in registers for stage 3
-  stage2(r_own, true);
-  store_w(i_own, g_own);
+  // own node last so that G, L, R, m_phi stay in registers for stage 3 (a thread past the
+  // top wall, oy >= ny, stores the ghost value and takes no part in stage 3)
+  if (wall_tile && oy >= ny) {
+    stage2(r_own - RX, true);
+    store_w(i_own, region_gidx(lx + 2, ly + 1, lz + HZ), T(-1));
+  } else {
+    stage2(r_own, true);
+    store_w(i_own, g_own, T(1));
+  }
   __syncthreads();
 
   if (!valid) return;
@@ -697,6 +776,8 @@ __global__ void __launch_bounds__(TileShape<LAT>::NT) nphase_step_kernel(const S
     } else {
       Z[0] = Z[1] = Z[2] = 0;
     }
+    const bool wall_lo = (D == 2) && a.walls && oy == 0;
+    const bool wall_hi = (D == 2) && a.walls && oy == ny - 1;
     auto dest = [&](int i) -> unsigned {
       return (unsigned)X[L::c(i, 0) + 1] +
              (unsigned)nx * ((unsigned)Y[L::c(i, 1) + 1] + (unsigned)ny * (unsigned)Z[L::c(i, 2) + 1]);
@@ -769,6 +850,7 @@ __global__ void __launch_bounds__(TileShape<LAT>::NT) nphase_step_kernel(const S
       }
       const T wi = T(L::w(i));
       const T geq = wi * (T(3) * P + T(3) * rho * cu + T(4.5) * cm * cu - T(1.5) * mu_dot);
+      // toward a wall: bounce-back into the opposite direction at the own node
       const T Fi = wi * (ugr + T(3) * cF + T(4.5) * (cTc - CS2 * trT));
       T corr = T(0);
       if (cnorm2<L>(i) == 1) {
@@ -783,7 +865,9 @@ __global__ void __launch_bounds__(TileShape<LAT>::NT) nphase_step_kernel(const S
             if (L::c(i, d) != 0 && L::c(i, e) != 0)
               corr = T(0.25) * T(L::c(i, d) * L::c(i, e)) * Nn[d][e];
       }
-      ST(a.g_dst, i - 1, dest(i), geq + T(0.5) * Fi + oms2 * corr);
+      const bool bb = (L::c(i, 1) == -1 && wall_lo) || (L::c(i, 1) == 1 && wall_hi);
+      ST(a.g_dst, bb ? opposite<L>(i) - 1 : i - 1, bb ? (unsigned)g_own : dest(i),
+         geq + T(0.5) * Fi + oms2 * corr);
     }
 #pragma unroll
     for (int d = 0; d < D; ++d) {

@@ -1,0 +1,126 @@
+"""GPU parity with walls (D2Q9): half-way bounce-back below row 0 and above row ny - 1 and
+the N-phase wetting condition with Young's relation, through the C ABI, against the FP64
+oracle on the same seeded inputs.
+
+Bars (as for the periodic box): FP64 max |dphi| <= 1e-12 and max |du| / max |u|,
+max |dP| / max |P| <= 1e-12; FP64 mass conserved to 1e-12; FP32 max |dphi| <= 2e-5 and
+per-phase relative mass drift <= 1e-6.  The FP64 export of the state (save_state64) must
+equal the oracle's post-stream populations, the bounced-back ones at the walls included.
+Grids are ragged (ny not a multiple of the 8-row tile, so a tile holds rows past the top
+wall) or tile-exact, down to ny = 2 where both walls touch the same tile row pair."""
+import math
+
+import numpy as np
+import pytest
+
+from _helpers import errors, ragged_discs, run_gpu, run_oracle
+from paper_2306_06983_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32_PHI_TOL = 2e-5
+FP32_MASS_TOL = 1e-6
+HDR = 256
+
+
+def _walled(cfg, cos_pN):
+    cfg = dict(cfg)
+    cfg["walls"] = True
+    cfg["contact_cos"] = [float(c) for c in cos_pN]
+    return cfg
+
+
+def _sessile_drop(nx=48, ny=24, theta_deg=60.0):
+    """Half-disc R = 10 of phase 0 on the bottom wall, phase 1 around it."""
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    r = np.hypot(x - nx / 2 + 0.5, y + 0.5)
+    p1 = 0.5 + 0.5 * np.tanh(2.0 * (10.0 - r) / 3.0)
+    cfg = inputs.base_cfg("D2Q9", nx, ny, 1, 2, [[0, 0.01], [0.01, 0]], [2.0, 1.0],
+                          [0.8, 0.8], mobility=0.1, eps=3.0, model="B")
+    return _walled(cfg, [math.cos(math.radians(theta_deg))]), np.stack([p1, 1 - p1])
+
+
+def _random_mixture(nx, ny, N=3, seed=3):
+    """Every phase present at every node (a generic, non-smooth state)."""
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(0.2, 1.0, size=(N, ny, nx))
+    sig = inputs.random_sigma(N, rng, 0.005, 0.02)
+    cfg = inputs.base_cfg("D2Q9", nx, ny, 1, N, sig, [2.0, 3.0, 1.0][:N], [0.8, 0.7, 0.9][:N],
+                          mobility=0.03, eps=3.0, model="B")
+    return _walled(cfg, [0.5, -0.4][:N - 1]), a / a.sum(0)
+
+
+def _discs(*args, cos_pN, **kw):
+    cfg, phi = ragged_discs(*args, **kw)
+    return _walled(cfg, cos_pN), phi
+
+
+CASES = {
+    "walls_B_N3_50x37": (lambda: _discs(50, 37, cos_pN=[0.4, -0.3]), 200),
+    "walls_A2_N4_solve_all_gravity_45x33": (
+        lambda: _discs(45, 33, N=4, model="A", model_a_n=2, solve_all=True, count=4,
+                       gravity=(0.0, -1e-5, 0.0), cos_pN=[0.3, -0.5, 0.1]), 150),
+    "walls_B_N2_drop_48x24": (lambda: _sessile_drop(), 200),
+    "walls_A1_N3_33x9": (lambda: _discs(33, 9, model="A", count=2, rmin=2.5, rmax=3.5,
+                                        cos_pN=[-0.2, 0.6]), 120),
+    "walls_B_N3_mixture_7x2": (lambda: _random_mixture(7, 2), 40),
+}
+
+
+@pytest.fixture(scope="module", params=sorted(CASES))
+def case(request):
+    build, steps = CASES[request.param]
+    cfg, phi = build()
+    print(f"\ncase {request.param} grid {cfg['nx']}x{cfg['ny']} N={cfg['n_phases']} "
+          f"model={cfg['model']} steps={steps}", flush=True)
+    return request.param, cfg, phi, steps, run_oracle(cfg, phi, steps)
+
+
+def test_walls_fp64_parity(case):
+    name, cfg, phi, steps, o = case
+    g = run_gpu(cfg, phi, steps)
+    dphi, du, dP = errors(g, o)
+    print(f"  fp64 dphi={dphi:.2e} du={du:.2e} dP={dP:.2e}")
+    assert g["finite"] and g["t"] == steps
+    assert dphi <= FP64_TOL
+    assert du <= FP64_TOL
+    assert dP <= FP64_TOL
+    assert np.allclose(g["m1"], o["m1"], rtol=1e-12, atol=1e-300)
+    assert np.all(np.abs(g["m1"] - g["m0"]) <= 1e-12 * np.abs(g["m0"]))
+
+
+def test_walls_fp32_parity(case):
+    name, cfg, phi, steps, o = case
+    g = run_gpu(cfg, phi, steps, precision="fp32")
+    dphi = float(np.abs(g["phi"] - o["phi"]).max())
+    drift = float(np.max(np.abs(g["m1"] - g["m0"]) / np.abs(g["m0"])))
+    print(f"  fp32 dphi={dphi:.2e} mass drift={drift:.2e}")
+    assert g["finite"] and g["t"] == steps
+    assert dphi <= FP32_PHI_TOL
+    assert drift <= FP32_MASS_TOL
+
+
+def test_walls_state64_matches_oracle_populations(case):
+    """The exported FP64 populations (phase sets f, flow set g without g_0) against the
+    oracle's post-stream state, entry by entry."""
+    import torch
+    from paper_2306_06983_amd import binding as B
+    name, cfg, phi, steps, o = case
+    nx, ny, N = cfg["nx"], cfg["ny"], cfg["n_phases"]
+    NS = N if cfg.get("solve_all", False) else N - 1
+    V, Q = nx * ny, 9
+    s = B.Sim(cfg, "fp64").init(phi)
+    s.step(steps)
+    buf = s.save_state64()
+    torch.cuda.synchronize()
+    pay = buf[HDR:].view(torch.float64).cpu().numpy()
+    s.close()
+    f = pay[:NS * Q * V].reshape(NS, Q, ny, nx)
+    g = pay[NS * Q * V:NS * Q * V + (Q - 1) * V].reshape(Q - 1, ny, nx)
+    st = o["state"]
+    ef = np.abs(f - st["f"]).max() / np.abs(st["f"]).max()
+    eg = np.abs(g - st["g"][1:]).max() / max(np.abs(st["g"][1:]).max(), 1e-300)
+    print(f"  state64: f {ef:.2e} g {eg:.2e}")
+    assert ef <= 1e-12
+    assert eg <= 1e-12
