@@ -1,7 +1,8 @@
 """Benchmark of the fused N-phase LBM step on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
-    python bench.py --only spheres_fp64|spheres_fp32|bands_fp32 [--steps K] [--warmup W]
+    python bench.py --only spheres_fp64|spheres_fp32|bands_fp32|rti_fp64|rti_fp32
+                    [--steps K] [--warmup W]
 
 Workload: 512 x 512 periodic D2Q9, N = 4 phases, 40 seeded non-overlapping discs radii
 U[10, 30] in an ambient phase, densities 1:2:3:4, sigma_pq U[0.005, 0.02], Model B
@@ -11,8 +12,10 @@ launch), inputs resident in HBM.  Prints ONE JSON line.
 
 value = FP64 Model B MLUPS (node updates per second / 1e6); the FP32 form, Model A and
 the oracle on the host (cpu_baseline) are reported beside it, and (unless --no-extra)
-the 256^3 D3Q19 N = 4 drops (FP64, FP32), the 2048^2 N = 5 layered bands (FP32) and the
-wall time of a differentiable 256^2 run (forward with checkpoints, adjoint backward).
+the 256^3 D3Q19 N = 4 drops (FP64, FP32), the 2048^2 N = 5 layered bands (FP32), the
+walled ternary Rayleigh-Taylor instability of Sec. 4.4 on 256 x 1024 (FP64, FP32; timing
+and the interface locations at T = 1, 2, 3) and the wall time of a differentiable 256^2
+run (forward with checkpoints, adjoint backward).
 `--only NAME` times one of those other workloads alone (for profiling) and prints its
 record instead of the line.  roofline: the step kernel is HBM-bound (no dense contraction); achieved = algorithmic bytes per launch
 (every persisted value read once and written once) / mean launch time measured with
@@ -120,6 +123,31 @@ def time_extra(cfg, phi, precision, steps, warmup, d, Q, NS, label):
         # by the next: bytes of this implementation beyond the algorithmic figure
         rec["moments_buffer_bytes_per_node_update"] = 2 * NS * (4 + (1 if ts == 4 else 0)) * ts
     return rec
+
+
+def rti_diagnostics(precision, model="B", T_marks=(1.0, 2.0, 3.0)):
+    """The walled ternary Rayleigh-Taylor run on 256 x 1024 to the given times T (the
+    paper's unit t / sqrt(d / (g At))): per phase the interface locations Y_av, Y_min and
+    Y_max (C-ABI diagnostics) in the paper's coordinate y / d, y in [-2d, 2d]."""
+    from paper_2306_06983_amd import binding as B
+    from paper_2306_06983_amd import inputs
+    cfg, phi, spt = inputs.ternary_rti(model=model)
+    d = cfg["nx"]
+    sim = B.Sim(cfg, precision).init(phi)
+    m0 = sim.mass()
+    out, done = {}, 0
+    for T in T_marks:
+        n = int(round(T * spt)) - done
+        sim.step(n)
+        done += n
+        av, lo, hi = sim.interface_locations()
+        to_y = lambda h: [round((float(v) + 0.5 - 2 * d) / d, 4) for v in h]
+        out[f"T={T:g}"] = {"steps": done, "Y_av": to_y(av), "Y_min": to_y(lo), "Y_max": to_y(hi)}
+    m1 = sim.mass()
+    out["finite"] = bool(sim.check())
+    out["mass_drift_rel"] = float(max(abs(m1 - m0) / abs(m0)))
+    sim.close()
+    return out
 
 
 def time_adjoint(steps=25, ckpt_every=10):
@@ -230,7 +258,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the 3D, 2048^2 and adjoint workloads reported beside the line")
-    ap.add_argument("--only", choices=["spheres_fp64", "spheres_fp32", "bands_fp32"],
+    ap.add_argument("--only", choices=["spheres_fp64", "spheres_fp32", "bands_fp32",
+                                       "rti_fp64", "rti_fp32"],
                     help="time only this other workload and print its record")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 256 MiB ten times (reference "
@@ -257,9 +286,15 @@ def main():
         return time_extra(c4, p4, prec, steps, warm, 2, 9, c4["n_phases"] - 1,
                           "layered_bands_2048x2048_N5_d2q9")
 
+    def rti(prec, steps, warm):
+        c5, p5, _ = inputs.ternary_rti()   # 256 x 1024 D2Q9, N = 3, walls, gravity
+        return time_extra(c5, p5, prec, steps, warm, 2, 9, c5["n_phases"] - 1,
+                          "ternary_rti_walls_256x1024_N3_d2q9")
+
     if args.only:
         kind, prec = args.only.split("_")
-        rec = (spheres if kind == "spheres" else bands)(prec, args.steps, args.warmup)
+        rec = {"spheres": spheres, "bands": bands, "rti": rti}[kind](prec, args.steps,
+                                                                      args.warmup)
         print(json.dumps(rec))
         return 0
 
@@ -333,7 +368,10 @@ def main():
     }
     if not args.no_extra:
         line["other_workloads"] = [spheres("fp64", 100, 10), spheres("fp32", 100, 10),
-                                   bands("fp32", 500, 50)]
+                                   bands("fp32", 500, 50), rti("fp64", 2000, 200),
+                                   rti("fp32", 2000, 200)]
+        line["rti_ternary_diagnostics"] = {"fp64": rti_diagnostics("fp64"),
+                                           "fp32": rti_diagnostics("fp32")}
         line["adjoint"] = time_adjoint()
     if not args.no_cpu:
         cb = time_oracle(cfg, phi)

@@ -145,6 +145,17 @@ int nphase_lbm_fields(nphase_lbm_t h, double *phi_dev, double *u_dev, double *p_
  * Writes N doubles to mass_host.  Synchronises the stream. */
 int nphase_lbm_mass(nphase_lbm_t h, double *mass_host);
 
+/* Interface locations of each phase (the diagnostics of Sec. 4.4) from N order parameters
+ * phi_dev [N][nz][ny][nx] (FP64, device; e.g. the phi output of nphase_lbm_fields), with
+ * the height h of a node = its row index y on D2Q9, its plane index z on D3Q19:
+ *   y_av_host[p]  = sum_x h phi_p / sum_x phi_p (FP64, fixed reduction order; NaN when
+ *                   sum_x phi_p = 0),
+ *   y_min_host[p] = the lowest h holding a node with phi_p >= 1/2 (-1 if there is none),
+ *   y_max_host[p] = the highest such h (-1 if there is none).
+ * N entries each (host).  Uses the handle's reduction scratch; synchronises the stream. */
+int nphase_lbm_interface_locations(nphase_lbm_t h, const double *phi_dev, double *y_av_host,
+                                   int32_t *y_min_host, int32_t *y_max_host);
+
 /* all_finite_host = 1 if every phi^{t-1} and u value of the state is finite, else 0
  * and the call returns NPHASE_ENAN.  Synchronises the stream. */
 int nphase_lbm_check(nphase_lbm_t h, int *all_finite_host);

@@ -571,6 +571,28 @@ def fields(C, state):
     return mac["phi"], mac["u"], mac["P"]
 
 
+def interface_locations(phi, d):
+    """Sec. 4.4 diagnostics of each phase p over the grid: Y_av = sum_x h phi_p / sum_x phi_p,
+    Y_min / Y_max = the lowest / highest height h holding a node with phi_p >= 1/2.  The
+    height h is the node's row index y (2D, phi [N, ny, nx]) or plane index z (3D,
+    phi [N, nz, ny, nx]).  Y_av is NaN for a phase with zero sum, Y_min = Y_max = -1 for a
+    phase below 1/2 everywhere."""
+    phi = np.asarray(phi, dtype=np.float64)
+    N = phi.shape[0]
+    nh = phi.shape[1]
+    h = np.arange(nh, dtype=np.float64).reshape((nh,) + (1,) * (d - 1))
+    y_av = np.empty(N)
+    y_min = np.empty(N, dtype=np.int64)
+    y_max = np.empty(N, dtype=np.int64)
+    for p in range(N):
+        tot = phi[p].sum()
+        y_av[p] = (h * phi[p]).sum() / tot if tot != 0.0 else np.nan
+        rows = np.flatnonzero((phi[p] >= 0.5).reshape(nh, -1).any(axis=1))
+        y_min[p] = rows[0] if rows.size else -1
+        y_max[p] = rows[-1] if rows.size else -1
+    return y_av, y_min, y_max
+
+
 def mass(C, state):
     """Per-phase mass sum_x phi_p for all N phases."""
     phi = all_phases(C, state["f"].sum(axis=1))

@@ -74,6 +74,9 @@ def load():
         "nphase_lbm_fields": [vp, vp, vp, vp],
         "nphase_lbm_mass": [vp, ctypes.POINTER(ctypes.c_double)],
         "nphase_lbm_check": [vp, ctypes.POINTER(ctypes.c_int)],
+        "nphase_lbm_interface_locations": [vp, vp, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_int32)],
         "nphase_lbm_time": [vp, ctypes.POINTER(i64)],
         "nphase_lbm_state_bytes": [vp, ctypes.POINTER(sz)],
         "nphase_lbm_save_state": [vp, vp],
@@ -201,6 +204,23 @@ class Sim:
         out = (ctypes.c_double * self.N)()
         self._rc(self.lib.nphase_lbm_mass(self.h, out))
         return np.array(out[:], dtype=np.float64)
+
+    def interface_locations(self, phi=None):
+        """(Y_av [N] float, Y_min [N] int, Y_max [N] int) of FP64 device phase fields
+        phi [N, *grid] (default: the current fields); heights are row (2D) / plane (3D)
+        indices."""
+        if phi is None:
+            phi = self.fields()[0]
+        phi = phi.contiguous()
+        assert phi.dtype == self.torch.float64 and phi.is_cuda
+        assert tuple(phi.shape) == (self.N,) + self.grid
+        av = (ctypes.c_double * self.N)()
+        lo = (ctypes.c_int32 * self.N)()
+        hi = (ctypes.c_int32 * self.N)()
+        self._rc(self.lib.nphase_lbm_interface_locations(self.h, ctypes.c_void_p(phi.data_ptr()),
+                                                         av, lo, hi))
+        return (np.array(av[:], dtype=np.float64), np.array(lo[:], dtype=np.int64),
+                np.array(hi[:], dtype=np.int64))
 
     def check(self):
         ok = ctypes.c_int(0)

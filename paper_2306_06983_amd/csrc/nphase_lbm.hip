@@ -78,7 +78,9 @@ Layout layout_of(const nphase_lbm_params& p) {
   // by every step
   L.mo = p.lattice == NPHASE_D3Q19 ? align_up((size_t)NS * (4 + (ts == 4 ? 1 : 0)) * V * ts) : 0;
   L.partial = align_up((size_t)MAXN * RED_BLOCKS * sizeof(double));
-  L.mass = align_up(MAXN * sizeof(double));
+  // per-phase results of the reductions: mass (N), interface locations (3 MAXN)
+  L.mass = align_up(3 * MAXN * sizeof(double));
+  static_assert(4 * MAXN * LOC_BLOCKS <= MAXN * RED_BLOCKS, "location partials fit");
   L.flag = align_up(sizeof(int) * 4);
   L.total = 2 * (L.f + L.g + L.u) + L.mm + L.mo + L.partial + L.mass + L.flag;
   return L;
@@ -403,6 +405,34 @@ int nphase_lbm_mass(nphase_lbm_t h, double* mass_host) {
   HIPCHK(mass_async(h), "mass kernel");
   HIPCHK(hipMemcpyAsync(mass_host, h->mass_dev, sizeof(double) * h->N, hipMemcpyDeviceToHost, h->stream), "mass copy");
   HIPCHK(hipStreamSynchronize(h->stream), "mass sync");
+  return NPHASE_OK;
+}
+
+int nphase_lbm_interface_locations(nphase_lbm_t h, const double* phi_dev, double* y_av_host,
+                                   int32_t* y_min_host, int32_t* y_max_host) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!phi_dev || !y_av_host || !y_min_host || !y_max_host) {
+    h->err = "NULL pointer";
+    return NPHASE_EINVAL;
+  }
+  const nphase_lbm_params& p = h->prm;
+  // height = row (D2Q9) or z plane (D3Q19): nodes per height level
+  const long long plane = h->lat == NPHASE_D2Q9 ? (long long)p.nx : (long long)p.nx * p.ny;
+  hipLaunchKernelGGL(locations_partial_kernel, dim3(LOC_BLOCKS), dim3(256), 0, h->stream,
+                     phi_dev, h->partial, h->N, (long long)h->V, plane);
+  hipLaunchKernelGGL(locations_final_kernel, dim3(h->N), dim3(LOC_BLOCKS), 0, h->stream,
+                     (const double*)h->partial, h->mass_dev);
+  HIPCHK(hipGetLastError(), "locations kernels");
+  double out[3 * MAXN];
+  HIPCHK(hipMemcpyAsync(out, h->mass_dev, sizeof(out), hipMemcpyDeviceToHost, h->stream),
+         "locations copy");
+  HIPCHK(hipStreamSynchronize(h->stream), "locations sync");
+  for (int q = 0; q < h->N; ++q) {
+    y_av_host[q] = out[q];
+    y_min_host[q] = (int32_t)out[MAXN + q];
+    y_max_host[q] = (int32_t)out[2 * MAXN + q];
+  }
   return NPHASE_OK;
 }
 

@@ -12,7 +12,9 @@ workload description that calls the ambient "phase 1" is therefore stored in the
 
 cfg dictionary keys (shared with the oracle and the binding):
   lattice ('D2Q9'|'D3Q19'), nx, ny, nz, n_phases, sigma (N x N nested list), rho (N),
-  tau_g (N), mobility, eps, model ('A'|'B'), model_a_n, solve_all, gravity (3 floats).
+  tau_g (N), mobility, eps, model ('A'|'B'), model_a_n, solve_all, gravity (3 floats),
+  and optionally walls (bool, D2Q9: walls below row 0 and above row ny - 1) and
+  contact_cos (N-1 floats, cos theta_pN).
 """
 import math
 
@@ -245,6 +247,51 @@ def static_droplets(model="B", model_a_n=1, absent=(), eps=5.0, nx=301, ny=101):
     cfg = base_cfg("D2Q9", nx, ny, 1, N, uniform_sigma(N, 0.01), rho, tau, eps=eps,
                    model=model, model_a_n=model_a_n)
     return cfg, phi
+
+
+def ternary_rti(nx=256, ny=1024, eps=4.0, mobility=0.02, U=0.04, model="B", binary=False,
+                model_a_n=1, Re=1000.0):
+    """Sec. 4.4 Rayleigh-Taylor instability between walls: the domain [-d/2, d/2] x [-2d, 2d]
+    with d = nx and ny = 4 d, periodic in x, no-flux walls below and above (90 degree
+    contact angles), At = 0.5 (rho_1 : rho_2 : rho_3 = 3 : 2 : 1), Re = d rho_3 sqrt(g d) /
+    mu_3 = 1000, Ca = mu_3 sqrt(g d) / sigma = 0.28, equal dynamic viscosities and one sigma
+    for every pair.  The paper leaves sqrt(g d), eps and M open: U = sqrt(g d) = 0.04,
+    eps = 4 and M = 0.02 by default.  Node (i, j) sits at x = i + 1/2 - d/2,
+    y = j + 1/2 - 2d; with H(s) = 1/2 + 1/2 tanh(2 s / eps):
+      ternary: phi_1 = H(y - 2d/3 - 0.1 d sin(2 pi x / d)),
+               phi_2 = (1 - phi_1) H(y + 2d/3 + 0.1 d sin(2 pi x / d));
+      binary:  phi_1 = H(y - 0.1 d cos(2 pi x / d)), phi_2 = 0.
+    A smaller d at the same relaxation times takes Re scaled with d (Re = 1000 d / 256).
+    Stored order: phases 1, 2, 3 (phase 3 = 1 - phi_1 - phi_2).  Returns cfg, phi and the
+    number of steps per unit of the paper's time T = t / sqrt(d / (g At))."""
+    d = float(nx)
+    g = U * U / d
+    rho = [3.0, 2.0, 1.0]
+    mu = d * rho[2] * U / Re
+    sigma = mu * U / 0.28
+    tau = [0.5 + 3.0 * mu / r for r in rho]
+    x = np.arange(nx, dtype=np.float64) + 0.5 - d / 2.0
+    y = np.arange(ny, dtype=np.float64) + 0.5 - 2.0 * d
+    Y, X = np.meshgrid(y, x, indexing="ij")
+
+    def H(s):
+        return 0.5 + 0.5 * np.tanh(2.0 * s / eps)
+
+    if binary:
+        p1 = H(Y - 0.1 * d * np.cos(2.0 * np.pi * X / d))
+        p2 = np.zeros_like(p1)
+    else:
+        wave = 0.1 * d * np.sin(2.0 * np.pi * X / d)
+        p1 = H(Y - 2.0 * d / 3.0 - wave)
+        p2 = (1.0 - p1) * H(Y + 2.0 * d / 3.0 + wave)
+    phi = np.stack([p1, p2, 1.0 - (p1 + p2)])
+    cfg = base_cfg("D2Q9", nx, ny, 1, 3, uniform_sigma(3, sigma), rho, tau,
+                   mobility=mobility, eps=eps, model=model, model_a_n=model_a_n,
+                   gravity=(0.0, -g, 0.0))
+    cfg["walls"] = True
+    cfg["contact_cos"] = [0.0, 0.0]
+    steps_per_T = math.sqrt(d / (g * 0.5))
+    return cfg, phi, steps_per_T
 
 
 def sigma_pairs(cfg):

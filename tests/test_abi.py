@@ -75,6 +75,11 @@ def test_workspace_bytes_d3q19(lib, precision, b, nmr, nm):
     (lambda p: setattr(p, "mobility", 0.0), B.NPHASE_EINVAL),
     (lambda p: setattr(p, "eps", float("nan")), B.NPHASE_EINVAL),
     (lambda p: p.gravity.__setitem__(1, float("inf")), B.NPHASE_EINVAL),
+    (lambda p: setattr(p, "walls", 2), B.NPHASE_EINVAL),
+    (lambda p: (setattr(p, "walls", 1), p.contact_cos.__setitem__(1, 1.5)), B.NPHASE_EINVAL),
+    (lambda p: (setattr(p, "walls", 1), p.contact_cos.__setitem__(0, float("nan"))),
+     B.NPHASE_EINVAL),
+    (lambda p: (setattr(p, "walls", 1), setattr(p, "ny", 1)), B.NPHASE_EINVAL),
 ])
 def test_invalid_parameters_rejected(lib, mutate, code):
     cfg, _ = inputs.two_discs()
@@ -94,6 +99,17 @@ def test_unsupported_phase_count(lib):
                           [0.8] * N)
     rc, _ = _ws(lib, B.make_params(cfg))
     assert rc == B.NPHASE_ENOTSUP
+
+
+def test_walls_d3q19_unsupported(lib):
+    cfg = inputs.base_cfg("D3Q19", 16, 16, 16, 3, inputs.uniform_sigma(3, 0.01), [1.0] * 3,
+                          [0.8] * 3)
+    cfg["walls"] = True
+    rc, _ = _ws(lib, B.make_params(cfg))
+    assert rc == B.NPHASE_ENOTSUP
+    cfg["lattice"], cfg["nz"] = "D2Q9", 1
+    rc, _ = _ws(lib, B.make_params(cfg))
+    assert rc == B.NPHASE_OK
 
 
 def test_create_checks_workspace_without_device_work(lib):

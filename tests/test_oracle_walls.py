@@ -199,3 +199,58 @@ def test_sessile_drop_relaxes_to_contact_angle(theta_deg):
     phi, _, _ = O.fields(C, st)
     th = _drop_angle(phi[0])
     assert abs(th - theta_deg) <= 3.0, th
+
+
+def _locations_loops(phi):
+    """Per-node loops over a 2D field [N, ny, nx]: sum y phi, sum phi, rows with phi >= 1/2."""
+    N, ny, nx = phi.shape
+    out = []
+    for p in range(N):
+        sy = s = 0.0
+        rows = []
+        for y in range(ny):
+            for x in range(nx):
+                v = float(phi[p, y, x])
+                sy += y * v
+                s += v
+                if v >= 0.5:
+                    rows.append(y)
+        out.append((sy / s if s != 0.0 else float("nan"),
+                    min(rows) if rows else -1, max(rows) if rows else -1))
+    return out
+
+
+def test_interface_locations_closed_forms():
+    """Sec. 4.4 diagnostics: a band of phase 0 on rows 2..4 (Y_av = 3 exactly), a lone node
+    at exactly 1/2 on row 7 counts as reached, an absent phase gives NaN and -1, a profile
+    symmetric about the centre has Y_av at the centre; 3D uses the z plane."""
+    ny, nx = 10, 5
+    phi = np.zeros((3, ny, nx))
+    phi[0, 2:5, :] = 1.0
+    phi[1] = 1.0 - phi[0]
+    phi[1, 7, 3] = 0.5
+    av, lo, hi = O.interface_locations(phi, 2)
+    assert av[0] == 3.0 and lo[0] == 2 and hi[0] == 4
+    assert lo[1] == 0 and hi[1] == 9
+    assert math.isnan(av[2]) and lo[2] == -1 and hi[2] == -1
+    y = np.arange(ny, dtype=float)
+    prof = np.exp(-((y - (ny - 1) / 2) / 2.0) ** 2)
+    av2, _, _ = O.interface_locations(np.repeat(prof[None, :, None], 4, axis=2), 2)
+    assert abs(av2[0] - (ny - 1) / 2) <= 1e-14
+    phi3 = np.zeros((2, 6, 3, 4))
+    phi3[0, 1:3] = 1.0
+    phi3[1] = 1.0 - phi3[0]
+    av3, lo3, hi3 = O.interface_locations(phi3, 3)
+    assert av3[0] == 1.5 and lo3[0] == 1 and hi3[0] == 2 and lo3[1] == 0 and hi3[1] == 5
+
+
+def test_interface_locations_match_loops():
+    """The vectorised diagnostics against per-node loops on a random field (values placed
+    on both sides of 1/2)."""
+    rng = np.random.default_rng(8)
+    phi = rng.uniform(0.0, 0.55, size=(3, 13, 9))
+    av, lo, hi = O.interface_locations(phi, 2)
+    ref = _locations_loops(phi)
+    for p in range(3):
+        assert abs(av[p] - ref[p][0]) <= 1e-13 * abs(ref[p][0])
+        assert lo[p] == ref[p][1] and hi[p] == ref[p][2]
