@@ -294,6 +294,37 @@ def ternary_rti(nx=256, ny=1024, eps=4.0, mobility=0.02, U=0.04, model="B", bina
     return cfg, phi, steps_per_T
 
 
+def compound_droplet(theta23_deg, theta13_deg=75.0, nx=300, ny=150, R=60.0, eps=5.0,
+                     mobility=0.1, model="B", model_a_n=1):
+    """Sec. 4.2 compound droplet spreading on a wall: domain [-150, 150] x [0, 150] (nodes at
+    x = i + 1/2 - nx/2, y = j + 1/2, the wall half a spacing below row 0), periodic in x,
+    walls below and above; a semicircle R = 60 on the bottom wall, phase 1 on its left half
+    and phase 2 on its right half, in phase 3:
+      phi_1 = H_R (1/2 - 1/2 tanh(2x/eps)), phi_2 = H_R (1/2 + 1/2 tanh(2x/eps)),
+      H_R = 1/2 + 1/2 tanh(2 (R - r) / eps), r = sqrt(x^2 + y^2).
+    Material data of the Sec. 4.1 ternary system: rho 1000:500:1, mu 100:50:0.1 (every
+    tau_g = 0.8), sigma_pq = 0.01, eps = 5; contact angles theta_13 (75 degrees) and
+    theta_23 against phase 3, the 1-2 pair from Young's relation.  M is not given in the
+    paper (0.1 here, tau_f = 0.8).  Stored order: phases 1, 2, 3."""
+    x = np.arange(nx, dtype=np.float64) + 0.5 - nx / 2.0
+    y = np.arange(ny, dtype=np.float64) + 0.5
+    Y, X = np.meshgrid(y, x, indexing="ij")
+    r = np.sqrt(X * X + Y * Y)
+    HR = 0.5 + 0.5 * np.tanh(2.0 * (R - r) / eps)
+    p1 = HR * (0.5 - 0.5 * np.tanh(2.0 * X / eps))
+    p2 = HR * (0.5 + 0.5 * np.tanh(2.0 * X / eps))
+    phi = np.stack([p1, p2, 1.0 - (p1 + p2)])
+    rho = [1000.0, 500.0, 1.0]
+    mu = [100.0, 50.0, 0.1]
+    tau = [0.5 + 3.0 * m / r_ for m, r_ in zip(mu, rho)]
+    cfg = base_cfg("D2Q9", nx, ny, 1, 3, uniform_sigma(3, 0.01), rho, tau, mobility=mobility,
+                   eps=eps, model=model, model_a_n=model_a_n)
+    cfg["walls"] = True
+    cfg["contact_cos"] = [math.cos(math.radians(theta13_deg)),
+                          math.cos(math.radians(theta23_deg))]
+    return cfg, phi
+
+
 def sigma_pairs(cfg):
     """Pair tensions sigma_pq (p < q) in lexicographic order."""
     s = np.asarray(cfg["sigma"])

@@ -70,3 +70,26 @@ def ragged_spheres(nx, ny, nz, N=4, seed=8, model="B", model_a_n=1, rho=None,
                           model_a_n=model_a_n, solve_all=solve_all, gravity=gravity)
     phi = inputs.balls_to_phases((nx, ny, nz), N, balls, 4.0)
     return cfg, phi
+
+
+def wetted_length(row):
+    """Length of the set {phi >= 1/2} along one row of nodes (unit spacing), each end
+    located by linear interpolation between the nodes on either side of 1/2; the set may
+    wrap around the periodic x boundary.  Returns 0 for an empty set."""
+    row = np.asarray(row, dtype=np.float64)
+    inside = row >= 0.5
+    n = row.size
+    if not inside.any():
+        return 0.0
+    if inside.all():
+        return float(n)
+    total = float(inside.sum())
+    # each boundary between an inside node k and an outside neighbour adds the fraction
+    # of the spacing where the linear interpolant is still >= 1/2
+    for k in range(n):
+        if not inside[k]:
+            continue
+        for nb in ((k - 1) % n, (k + 1) % n):
+            if not inside[nb]:
+                total += (row[k] - 0.5) / (row[k] - row[nb]) - 0.5
+    return total
