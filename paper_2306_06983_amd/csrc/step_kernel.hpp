@@ -101,6 +101,32 @@ struct TileShape<LAT_D3Q19> {   // used by the tile kernel only if instantiated 
   static constexpr int NT = TX * TY * TZ;        // z-marching kernel (step3d_kernel.hpp)
 };
 
+// LDS bytes of the D2Q9 fused kernel with a 32 x TY_ tile (the arrays declared in it)
+template <typename T, int N, bool SA, int MODEL, int TY_>
+constexpr size_t step2d_lds_bytes() {
+  constexpr int TX = 32, NS = SA ? N : N - 1, NP = N * (N - 1) / 2, NF = 5;
+  constexpr size_t NE = (TX + 6) * (TY_ + 6), NR = (TX + 4) * (TY_ + 4), NI = (TX + 2) * (TY_ + 2);
+  constexpr size_t MRB = sizeof(T) * NS * NF * NE;
+  constexpr size_t PWB = sizeof(T) * ((MODEL == MODEL_B ? NP : 0) * NR + NI);
+  return (MRB > PWB ? MRB : PWB) + sizeof(T) * NS * NR;
+}
+// Tile of one instantiation.  D2Q9 takes 32 x 16 nodes (512 threads, one workgroup per CU)
+// where the LDS of 32 x 8 already limits a CU to two workgroups (8 waves) and the taller
+// tile still fits: the same waves per CU with less halo recomputed per node (measured 5 %
+// on 512^2 FP64 N = 4).  Where 32 x 8 allows three or more workgroups the short tile stays
+// (a 2048^2 FP32 N = 5 step lost 35 % to a tall tile at fewer waves per CU), and so does
+// N > 4, whose registers do not fit two waves per SIMD.
+template <typename T, int LAT, int N, bool SA, int MODEL>
+struct StepTile {
+  static constexpr bool TALL = LAT == LAT_D2Q9 && N <= 4 &&
+                               step2d_lds_bytes<T, N, SA, MODEL, 8>() > (size_t)163840 / 3 &&
+                               step2d_lds_bytes<T, N, SA, MODEL, 16>() <= (size_t)163840;
+  static constexpr int TX = TileShape<LAT>::TX;
+  static constexpr int TY = TALL ? 16 : TileShape<LAT>::TY;
+  static constexpr int TZ = TileShape<LAT>::TZ;
+  static constexpr int NT = TX * TY * TZ;
+};
+
 __device__ __forceinline__ int wrap(int v, int n) {
   int r = v % n;
   return r < 0 ? r + n : r;
@@ -197,14 +223,15 @@ __device__ __forceinline__ T pair_fraction(T pp, T pq) {
 }
 
 template <typename T, int LAT, int N, bool SA, int MODEL, int MODE>
-__global__ void __launch_bounds__(TileShape<LAT>::NT) nphase_step_kernel(const StepArgs<T> a) {
+__global__ void __launch_bounds__((StepTile<T, LAT, N, SA, MODEL>::NT))
+    nphase_step_kernel(const StepArgs<T> a) {
   using L = Lattice<LAT>;
   constexpr int D = L::D;
   constexpr int Q = L::Q;
   constexpr int NS = SA ? N : N - 1;
   constexpr int NP = N * (N - 1) / 2;
   constexpr bool DEV = sizeof(T) == 4;   // FP32 deviation storage
-  using TS = TileShape<LAT>;
+  using TS = StepTile<T, LAT, N, SA, MODEL>;
   constexpr int TX = TS::TX, TY = TS::TY, TZ = (D == 3) ? TS::TZ : 1;
   constexpr int NTH = TS::NT;   // threads per workgroup, one node each
   constexpr int RX = TX + 4, RY = TY + 4, RZ = (D == 3) ? TZ + 4 : 1;
