@@ -110,17 +110,23 @@ constexpr size_t step2d_lds_bytes() {
   constexpr size_t PWB = sizeof(T) * ((MODEL == MODEL_B ? NP : 0) * NR + NI);
   return (MRB > PWB ? MRB : PWB) + sizeof(T) * NS * NR;
 }
-// Tile of one instantiation.  D2Q9 takes 32 x 16 nodes (512 threads, one workgroup per CU)
-// where the LDS of 32 x 8 already limits a CU to two workgroups (8 waves) and the taller
-// tile still fits: the same waves per CU with less halo recomputed per node (measured 5 %
-// on 512^2 FP64 N = 4).  Where 32 x 8 allows three or more workgroups the short tile stays
-// (a 2048^2 FP32 N = 5 step lost 35 % to a tall tile at fewer waves per CU), and so does
-// N > 4, whose registers do not fit two waves per SIMD.
+// Tile of one instantiation.  D2Q9 takes 32 x 16 nodes (512 threads) where that keeps the
+// waves per CU of 32 x 8, with less halo recomputed per node: FP64 where the LDS of 32 x 8
+// already limits a CU to two workgroups (8 waves) and 32 x 16 fits one (measured 5 % on
+// 512^2 N = 4), FP32 where two 32 x 16 workgroups fit, with registers bounded for 4 waves
+// per SIMD (7-8 % on 512^2 N = 4, 5 % on the 256 x 1024 N = 3 walled box).  N > 4 keeps
+// 32 x 8: its registers do not allow those waves (a 2048^2 FP32 N = 5 step lost 35 % to a
+// tall tile at fewer waves per CU).
 template <typename T, int LAT, int N, bool SA, int MODEL>
 struct StepTile {
-  static constexpr bool TALL = LAT == LAT_D2Q9 && N <= 4 &&
-                               step2d_lds_bytes<T, N, SA, MODEL, 8>() > (size_t)163840 / 3 &&
-                               step2d_lds_bytes<T, N, SA, MODEL, 16>() <= (size_t)163840;
+  static constexpr bool TALL64 = sizeof(T) == 8 &&
+                                 step2d_lds_bytes<T, N, SA, MODEL, 8>() > (size_t)163840 / 3 &&
+                                 step2d_lds_bytes<T, N, SA, MODEL, 16>() <= (size_t)163840;
+  static constexpr bool TALL32 = sizeof(T) == 4 &&
+                                 step2d_lds_bytes<T, N, SA, MODEL, 16>() <= (size_t)163840 / 2;
+  static constexpr bool TALL = LAT == LAT_D2Q9 && N <= 4 && (TALL64 || TALL32);
+  // FP32 tall tiles: registers for 4 waves per SIMD (two workgroups per CU)
+  static constexpr int MINW = (TALL && sizeof(T) == 4) ? 4 : 1;
   static constexpr int TX = TileShape<LAT>::TX;
   static constexpr int TY = TALL ? 16 : TileShape<LAT>::TY;
   static constexpr int TZ = TileShape<LAT>::TZ;
@@ -223,7 +229,8 @@ __device__ __forceinline__ T pair_fraction(T pp, T pq) {
 }
 
 template <typename T, int LAT, int N, bool SA, int MODEL, int MODE>
-__global__ void __launch_bounds__((StepTile<T, LAT, N, SA, MODEL>::NT))
+__global__ void __launch_bounds__((StepTile<T, LAT, N, SA, MODEL>::NT),
+                                  (StepTile<T, LAT, N, SA, MODEL>::MINW))
     nphase_step_kernel(const StepArgs<T> a) {
   using L = Lattice<LAT>;
   constexpr int D = L::D;
