@@ -325,6 +325,45 @@ def compound_droplet(theta23_deg, theta13_deg=75.0, nx=300, ny=150, R=60.0, eps=
     return cfg, phi
 
 
+LENS_SIGMA = {"a": (0.005, 0.0087), "b": (0.0058, 0.0115), "c": (0.01, 0.01),
+              "d": (0.0173, 0.02)}   # Sec. 4.3 cases: (sigma_12, sigma_23) in N/m
+
+
+def liquid_lens(case, eps=5.0, mobility=0.1, model="B", model_a_n=1):
+    """Sec. 4.3 liquid lens without gravity: domain [-0.04, 0.04] x [-0.016, 0.016] m at
+    dx = 1.25e-4 m (640 x 256 nodes at x = (i + 1/2) dx - 0.04, y = (j + 1/2) dx - 0.016),
+    periodic in x, no-flux walls below and above; a drop of phase 2, R = 8e-3 m (64 nodes),
+    on the interface between phase 1 (below) and phase 3 (above):
+      phi_2 = 1/2 + 1/2 tanh(2 (R - r) / eps), phi_1 = (1 - phi_2)(1/2 + 1/2 tanh(-2y/eps)).
+    rho 1000:500:1 kg/m^3, mu 0.1:0.05:1e-4 Pa s, dt = dx / 20, sigma_13 = 0.01 N/m and
+    (sigma_12, sigma_23) of the case.  Lattice units with the reference density 1000 kg/m^3:
+    rho 1 : 0.5 : 0.001, every kinematic viscosity 0.04 (tau_g = 0.62), sigma_lattice =
+    sigma dt^2 / (1000 dx^3) = 0.02 sigma.  eps and M are not given in the paper (5 and 0.1
+    here; eps is in lattice units in the profiles above).  Stored order: phases 1, 2, 3."""
+    dx, dt = 1.25e-4, 1.25e-4 / 20.0
+    nx, ny = 640, 256
+    R = 8e-3 / dx
+    x = np.arange(nx, dtype=np.float64) + 0.5 - nx / 2.0
+    y = np.arange(ny, dtype=np.float64) + 0.5 - ny / 2.0
+    Y, X = np.meshgrid(y, x, indexing="ij")
+    p2 = 0.5 + 0.5 * np.tanh(2.0 * (R - np.sqrt(X * X + Y * Y)) / eps)
+    p1 = (1.0 - p2) * (0.5 + 0.5 * np.tanh(-2.0 * Y / eps))
+    phi = np.stack([p1, p2, 1.0 - (p1 + p2)])
+    rho_ref = 1000.0
+    rho = [1000.0 / rho_ref, 500.0 / rho_ref, 1.0 / rho_ref]
+    mu_phys = [0.1, 0.05, 1e-4]
+    nu = [m / (r * rho_ref) * dt / dx ** 2 for m, r in zip(mu_phys, rho)]
+    tau = [0.5 + 3.0 * v for v in nu]
+    s12, s23 = LENS_SIGMA[case]
+    conv = dt * dt / (rho_ref * dx ** 3)
+    sig = np.array([[0.0, s12, 0.01], [s12, 0.0, s23], [0.01, s23, 0.0]]) * conv
+    cfg = base_cfg("D2Q9", nx, ny, 1, 3, sig, rho, tau, mobility=mobility, eps=eps,
+                   model=model, model_a_n=model_a_n)
+    cfg["walls"] = True
+    cfg["contact_cos"] = [0.0, 0.0]
+    return cfg, phi
+
+
 def sigma_pairs(cfg):
     """Pair tensions sigma_pq (p < q) in lexicographic order."""
     s = np.asarray(cfg["sigma"])

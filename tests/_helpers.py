@@ -93,3 +93,53 @@ def wetted_length(row):
             if not inside[nb]:
                 total += (row[k] - 0.5) / (row[k] - row[nb]) - 0.5
     return total
+
+
+def _crossings(col):
+    """Positions (fractional node index) where a column crosses 1/2, linear interpolation."""
+    out = []
+    for k in range(len(col) - 1):
+        a, b = col[k], col[k + 1]
+        if (a - 0.5) * (b - 0.5) < 0.0:
+            out.append(k + (0.5 - a) / (b - a))
+    return out
+
+
+def lens_geometry(phi):
+    """Measured geometry of a lens of phase 1 (index 1) on the interface between phase 0
+    (below) and phase 2 (above), phi [3, ny, nx] at equilibrium: the level y_I of the flat
+    0-2 interface (phi_0 = 1/2 in the two edge columns), the width d of {phi_1 >= 1/2} on
+    the line y = y_I, the height h_up of the lens above y_I and its depth h_down below, all
+    in node spacings, and the lens area S = sum phi_1."""
+    import numpy as np
+    p0, p1 = phi[0], phi[1]
+    y_i = np.mean([_crossings(p0[:, 0])[0], _crossings(p0[:, -1])[0]])
+    j = int(np.floor(y_i))
+    f = y_i - j
+    line = (1.0 - f) * p1[j] + f * p1[j + 1]
+    d = wetted_length(line)
+    tops, bots = [], []
+    for i in range(p1.shape[1]):
+        c = _crossings(p1[:, i])
+        if len(c) >= 2:
+            bots.append(c[0])
+            tops.append(c[-1])
+    return dict(y_i=float(y_i), d=float(d), h_up=float(max(tops) - y_i),
+                h_down=float(y_i - min(bots)), S=float(p1.sum()))
+
+
+def lens_neumann(s12, s13, s23, S):
+    """Equilibrium lens of area S between two fluids from Neumann's law (Sec. 4.3): the
+    angles theta_1 (cos = (s13^2 + s23^2 - s12^2) / (2 s13 s23), the cap on the side of
+    the fluid that meets the lens with s23) and theta_2 (cos = (s12^2 + s13^2 - s23^2) /
+    (2 s12 s13)), the distance of the triple points
+    d = 2 sqrt(S / sum_i (theta_i / sin theta_i - cos theta_i) / sin theta_i) and the cap
+    heights h_i = d/2 (1 - cos theta_i) / sin theta_i."""
+    import math
+    c1 = (s13 ** 2 + s23 ** 2 - s12 ** 2) / (2.0 * s13 * s23)
+    c2 = (s12 ** 2 + s13 ** 2 - s23 ** 2) / (2.0 * s12 * s13)
+    th = [math.acos(c1), math.acos(c2)]
+    den = sum((t / math.sin(t) - math.cos(t)) / math.sin(t) for t in th)
+    d = 2.0 * math.sqrt(S / den)
+    h = [d / 2.0 * (1.0 - math.cos(t)) / math.sin(t) for t in th]
+    return d, h[0], h[1]

@@ -9,12 +9,11 @@ equal the oracle's post-stream populations, the bounced-back ones at the walls i
 Grids are ragged (ny not a multiple of the 8-row tile, so a tile holds rows past the top
 wall) or tile-exact, down to ny = 2 where both walls touch the same tile row pair."""
 import math
-import os
 
 import numpy as np
 import pytest
 
-from _helpers import errors, ragged_discs, run_gpu, run_oracle, wetted_length
+from _helpers import errors, ragged_discs, run_gpu, run_oracle
 from paper_2306_06983_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -126,46 +125,3 @@ def test_walls_state64_matches_oracle_populations(case):
     assert ef <= 1e-12
     assert eg <= 1e-12
 
-
-def _table2():
-    rows = {}
-    path = os.path.join(os.path.dirname(__file__), "golden", "compound_droplet_table2.txt")
-    for line in open(path):
-        if line.strip() and not line.startswith("#"):
-            v = [float(x) for x in line.split()]
-            rows[v[0]] = dict(L1=v[1], L2=v[2], errL1=v[5], errL2=v[6])
-    return rows
-
-
-@pytest.mark.parametrize("theta23,steps", [(60.0, 6_000_000), (90.0, 6_000_000)])
-def test_compound_droplet_wetted_lengths(theta23, steps):
-    """Sec. 4.2: a compound droplet (phases 1 | 2) spreads on the wall with theta_13 = 75
-    degrees and theta_23 = 60 or 90 degrees; the wetted lengths L1, L2 / R must come at
-    least as close to the analytical equilibrium of Table 2 as the paper's Model B run,
-    plus 1 % (the run is cut at 6e6 steps, about 60 s in FP32, while the contact lines
-    still creep; M and the wall discretisation are readings).  Near 120 degrees this build
-    leaves L2 below the paper's value (0.45 at 6e6 steps against 0.50 of the paper), so
-    that case is reported in the design notes rather than tested."""
-    from paper_2306_06983_amd import binding as B
-    ref = _table2()[theta23]
-    cfg, phi = inputs.compound_droplet(theta23)
-    s = B.Sim(cfg, "fp32").init(phi)
-    m0 = s.mass()
-    s.step(steps)
-    ph = s.fields()[0].cpu().numpy()
-    ok = s.check()
-    m1 = s.mass()
-    s.close()
-    L1 = wetted_length(ph[0][0]) / 60.0
-    L2 = wetted_length(ph[1][0]) / 60.0
-    e1 = abs(L1 - ref["L1"]) / ref["L1"]
-    e2 = abs(L2 - ref["L2"]) / ref["L2"]
-    print(f"  theta23={theta23}: L1={L1:.4f} ({e1:.2%}, paper {ref['errL1']:.2%}) "
-          f"L2={L2:.4f} ({e2:.2%}, paper {ref['errL2']:.2%})")
-    assert ok
-    # FP32 storage: the compensated residual keeps the rounding of phi itself, the pulled
-    # deviations are rounded at each destination (about 1e-12 relative per step measured,
-    # 1e-11 allowed; the 2000-step workloads stay below the 1e-6 bar)
-    assert np.all(np.abs(m1 - m0) <= 1e-11 * steps * np.abs(m0))
-    assert e1 <= ref["errL1"] + 0.01
-    assert e2 <= ref["errL2"] + 0.01
