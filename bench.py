@@ -95,9 +95,10 @@ def time_gpu(cfg, phi, precision, steps, warmup):
     m1 = sim.mass()
     finite = sim.check()
     phi_out = sim.fields()[0]
+    loc = sim.interface_locations(phi_out)   # Sec. 4.4 diagnostics of the final state
     sim.close()
     return dict(ms_total=ms, ms_per_step=ms / steps, wall_s=wall, m0=m0, m1=m1,
-                finite=finite, phi=phi_out)
+                finite=finite, phi=phi_out, locations=loc)
 
 
 def time_extra(cfg, phi, precision, steps, warmup, d, Q, NS, label):
@@ -117,7 +118,12 @@ def time_extra(cfg, phi, precision, steps, warmup, d, Q, NS, label):
            "frac": round(gbs / HBM_PEAK_GBS, 4),
            "traffic": measured_traffic(label, precision), "finite": bool(r["finite"]),
            "moment_form_bytes_per_node_update": mf,
-           "moment_form_GBs": round(mlups * 1e6 * mf / 1e9, 1)}
+           "moment_form_GBs": round(mlups * 1e6 * mf / 1e9, 1),
+           # per phase after warm-up + timed steps: Y_av, Y_min, Y_max (rows / z planes)
+           "interface_locations": {"steps": steps + warmup,
+                                   "Y_av": [round(float(v), 3) for v in r["locations"][0]],
+                                   "Y_min": [int(v) for v in r["locations"][1]],
+                                   "Y_max": [int(v) for v in r["locations"][2]]}}
     if d == 3:
         # the per-node moments buffer (phi, j; FP32 residual) written by one pass and read
         # by the next: bytes of this implementation beyond the algorithmic figure
