@@ -1,5 +1,7 @@
-"""The paper's own equilibrium benchmarks with walls, on the GPU, against its printed tables:
+"""The paper's own equilibrium benchmarks, on the GPU, against its printed tables:
 
+  * Sec. 4.1, Table 1: E_L1 errors of static droplets (quaternary, ternary, binary), the
+    equality of Model A and Model B there, and the order of the spurious velocities;
   * Sec. 4.2, Table 2: wetted lengths of a compound droplet spreading on a wall (N-phase
     wetting condition with Young's relation);
   * Sec. 4.3, Table 3: length and heights of a liquid lens between two fluid layers
@@ -107,3 +109,52 @@ def test_liquid_lens_neumann(case):
     assert np.all(np.abs(m1 - m0) <= 1e-15 * 1_000_000 * np.abs(m0))
     for e, pe in zip(errs, ref["err"]):
         assert e <= pe + 0.015
+
+
+def _table1():
+    out = {}
+    path = os.path.join(os.path.dirname(__file__), "golden", "static_droplets_table1.txt")
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        sysname, phase, val = line.split()
+        out[(sysname, int(phase))] = float(val)
+    return out
+
+
+@pytest.mark.parametrize("system,absent", [("quaternary", ()), ("ternary", (3,)),
+                                           ("binary", (2, 3))])
+def test_static_droplets_table1(system, absent):
+    """Sec. 4.1, Table 1: three drops R = 20 (or two, or one: the reduction variants) in a
+    fourth phase, eps = 5, rho 1000:500:100:1, mu 100:50:10:0.1, 20000 steps (E_L1 moves
+    by 0.1 % between 2e4 and 3e5 steps).  Per phase, E_L1 = |phi - phi0|_1 / |phi0|_1
+    within 10 % of the printed value (measured 6-7 % below it for every phase and system;
+    the paper does not state M, the node placement or its step count); Model A (n = 1, 2)
+    and Model B give the same fields to 1e-6, as the paper reports the same errors for
+    them; absent phases stay exactly zero;
+    the spurious velocities are of the order 1e-7 the paper reports (max < 1e-6)."""
+    from paper_2306_06983_amd import binding as B
+    tab = _table1()
+    fields = {}
+    for model, n in (("B", 1), ("A", 1), ("A", 2)):
+        cfg, phi0 = inputs.static_droplets(model=model, model_a_n=n, absent=absent)
+        s = B.Sim(cfg, "fp64").init(phi0)
+        s.step(20000)
+        ph, u, _ = s.fields()
+        fields[(model, n)] = (ph.cpu().numpy(), float(u.abs().max()))
+        s.close()
+    ph, umax = fields[("B", 1)]
+    for p in range(4):
+        if (p + 1) in absent:
+            assert np.all(ph[p] == 0.0)
+            continue
+        e = np.abs(ph[p] - phi0[p]).sum() / np.abs(phi0[p]).sum()
+        ref = tab[(system, p + 1)]
+        print(f"  {system} phase {p + 1}: E_L1 {e:.4e} (paper {ref:.4e}, {e / ref - 1:+.1%})")
+        assert abs(e / ref - 1) <= 0.10
+    for key in (("A", 1), ("A", 2)):
+        # the same fields to 1e-6 (measured 5e-8: the models differ only where three phases
+        # overlap, in the tails of separated drops), so the same E_L1 to its printed digits
+        assert np.abs(fields[key][0] - ph).max() <= 1e-6
+    print(f"  max |u| = {umax:.2e}")
+    assert umax < 1e-6
