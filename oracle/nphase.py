@@ -40,12 +40,14 @@ Readings where the paper is silent (each listed in the design notes of the repos
   * rho_0 in lambda_0 is the constant RHO0 = 1;
   * initial state: f = f^eq(phi0, u=0), g = g^eq(P=0, u=0), u^{-1} = 0, phi^{-1} = phi0,
     m_phi^{-1} = 0;
-  * walls (D2Q9 only): solid below y = 0 and above y = ny - 1, each wall half-way between
-    the last fluid row and a ghost row; x stays periodic.  The stencils read ghost values
-    there: phi_p from the one-sided wetting condition with the wall normal pointing out of
-    the fluid, phi_p(ghost) = phi_p(row) + (4/eps) sum_{q != p} phi_p phi_q cos theta_pq at
-    the adjacent fluid row; the Model B pair fractions are formed from the ghost phi; the
-    tensor m_phi u^- - u^- m_phi is odd across the wall (it vanishes there with u).
+  * walls: solid beyond the first and the last plane of the slowest grid axis (rows
+    y = 0 and y = ny - 1 in 2D, planes z = 0 and z = nz - 1 in 3D), each wall half-way
+    between the last fluid plane and a ghost plane; the other axes stay periodic.  The
+    stencils read ghost values there: phi_p from the one-sided wetting condition with the
+    wall normal pointing out of the fluid, phi_p(ghost) = phi_p + (4/eps) sum_{q != p}
+    phi_p phi_q cos theta_pq at the adjacent fluid plane; the Model B pair fractions are
+    formed from the ghost phi; the tensor m_phi u^- - u^- m_phi is odd across the wall (it
+    vanishes there with u).
 """
 import numpy as np
 
@@ -65,8 +67,9 @@ class Config:
 
     cfg keys: lattice ('D2Q9'|'D3Q19'), nx, ny, nz, n_phases, sigma (N x N), rho (N),
     tau_g (N, per-phase fluid relaxation -> mu_p), mobility, eps, model ('A'|'B'),
-    model_a_n (integer >= 1), solve_all (bool), gravity (3 floats), walls (bool: D2Q9
-    half-way bounce-back walls below y = 0 and above y = ny - 1, x periodic), contact_cos
+    model_a_n (integer >= 1), solve_all (bool), gravity (3 floats), walls (bool:
+    half-way bounce-back walls at both ends of the slowest grid axis, y in 2D, z in 3D,
+    the other axes periodic), contact_cos
     (N-1 floats: cos theta_pN of each phase against the last one, Sec. 4.2).
     """
 
@@ -93,12 +96,13 @@ class Config:
         self.mu = self.rho * (self.tau_g - 0.5) * CS2
         # solved phase-field sets: all N, or the first N-1 (Sec. 4 intro)
         self.NS = self.N if self.solve_all else self.N - 1
-        # walls normal to y (D2Q9) with the N-1 independent contact angles theta_pN
+        # walls normal to the slowest grid axis (y in 2D, z in 3D) with the N-1
+        # independent contact angles theta_pN
         self.walls = bool(cfg.get("walls", False))
         cos_pN = list(cfg.get("contact_cos", [0.0] * (self.N - 1)))
         self.cos = young_cosines(self.sigma, cos_pN)
         if self.walls:
-            assert d == 2 and self.ny >= 2, "walls: D2Q9 with ny >= 2"
+            assert self.shape[0] >= 2, "walls: at least two planes between them"
 
 
 def young_cosines(sigma, cos_pN):
@@ -130,16 +134,23 @@ def shift(a, c):
 
 
 def neighbour(chi, c, ghost=None):
-    """chi(x + c).  ghost = None: periodic.  Otherwise (2D walls normal to y) ghost =
-    (lo, hi), the rows that stand below y = 0 and above y = ny - 1; x stays periodic."""
+    """chi(x + c).  ghost = None: periodic.  Otherwise (walls normal to the slowest grid
+    axis, velocity component d - 1) ghost = (lo, hi), the planes that stand before the
+    first and after the last plane of that axis; the other axes stay periodic."""
     if ghost is None:
         return shift(chi, c)
     lo, hi = ghost
-    ext = np.concatenate([lo[..., None, :], chi, hi[..., None, :]], axis=-2)
-    ext = np.roll(ext, -int(c[0]), axis=-1)
-    ny = chi.shape[-2]
-    cy = int(c[1])
-    return ext[..., 1 + cy:1 + cy + ny, :]
+    d = len(c)
+    gax = chi.ndim - d                      # array axis of the slowest grid axis
+    ext = np.concatenate([np.expand_dims(lo, gax), chi, np.expand_dims(hi, gax)], axis=gax)
+    for k in range(d - 1):                  # periodic axes
+        if c[k] != 0:
+            ext = np.roll(ext, -int(c[k]), axis=-(k + 1))
+    n = chi.shape[gax]
+    cw = int(c[d - 1])
+    sl = [slice(None)] * ext.ndim
+    sl[gax] = slice(1 + cw, 1 + cw + n)
+    return ext[tuple(sl)]
 
 
 def grad(chi, lat, ghost=None):
@@ -179,10 +190,10 @@ def wetting_ghost(C, row):
 
 
 def phi_ghosts(C, phi):
-    """(lo, hi) ghost rows of all N phases, or None without walls."""
+    """(lo, hi) ghost planes of all N phases, or None without walls."""
     if not C.walls:
         return None
-    return wetting_ghost(C, phi[:, 0, :]), wetting_ghost(C, phi[:, -1, :])
+    return wetting_ghost(C, phi[:, 0]), wetting_ghost(C, phi[:, -1])
 
 
 def _pick(ghost, p):
@@ -550,11 +561,12 @@ def _one_step(C, state):
         # half-way bounce-back (Sec. 4 intro): a population that would arrive from behind a
         # wall is the node's own post-collision population of the opposite direction
         opp = opposite(lat)
+        n_w = C.shape[0]
         for i in range(lat.Q):
-            row = {1: 0, -1: C.ny - 1}.get(int(lat.c[i, 1]))
-            if row is not None:
-                fnew[:, i, row, :] = fstar[:, opp[i], row, :]
-                gnew[i, row, :] = gstar[opp[i], row, :]
+            plane = {1: 0, -1: n_w - 1}.get(int(lat.c[i, lat.d - 1]))
+            if plane is not None:
+                fnew[:, i, plane] = fstar[:, opp[i], plane]
+                gnew[i, plane] = gstar[opp[i], plane]
     return {
         "f": fnew, "g": gnew,
         "u_prev": u.copy(),

@@ -19,8 +19,9 @@ velocity and Euler time derivatives (Sec. 3 closing paragraph); N-1 evolved sets
 M, diagonal S (Sec. 4 intro).  Readings where the paper is silent are the same as the
 vectorised oracle's (local tau_g, normal and pair-fraction guards, n_qp = -n_pq, the
 reconstructed phase treated as a field, first-index divergence, (rho - rho_bar) g,
-rho_0 = 1).  Walls (D2Q9): solid below y = 0 and above y = ny - 1 with half-way
-bounce-back (Sec. 4 intro); the stencils read ghost nodes behind a wall, whose order
+rho_0 = 1).  Walls: solid before the first and after the last plane of the slowest axis
+(rows of a 2D grid, z planes of a 3D one) with half-way bounce-back (Sec. 4 intro); the
+stencils read ghost nodes behind a wall, whose order
 parameters follow from the wetting condition of Sec. 4.2 at the adjacent fluid node (wall
 normal out of the fluid, one lattice spacing, contact angles from the Sec. 4.2 Young
 relation), pair fractions from those, and the tensor m_phi u^- - u^- m_phi with its sign
@@ -79,16 +80,17 @@ class Params:
                     self.cos[p][q] = (sig[p, last] * cN[p] - sig[q, last] * cN[q]) / sig[p, q]
 
     def ghost(self, Y):
-        """True for a node behind a wall (2D: row -1 or ny)."""
+        """True for a node behind a wall (index -1 or n of the slowest axis)."""
         return self.walls and not (0 <= Y[0] < self.shape[0])
 
     def facing(self, Y):
         """The fluid node in front of the ghost node Y."""
-        return (0 if Y[0] < 0 else self.shape[0] - 1, Y[1])
+        return (0 if Y[0] < 0 else self.shape[0] - 1,) + tuple(Y[1:])
 
     def nbr(self, X, c):
         """Array index of the node X + c (c in (x, y[, z]) order), periodic; with walls the
-        row is not wrapped, so a node behind a wall comes back as row -1 or ny."""
+        slowest axis (y in 2D, z in 3D) is not wrapped, so a node behind a wall comes back
+        with index -1 or n there."""
         if self.d == 2:
             y, x = X
             ny, nx = self.shape
@@ -96,7 +98,8 @@ class Params:
             return (yy, (x + int(c[0])) % nx)
         z, y, x = X
         nz, ny, nx = self.shape
-        return ((z + int(c[2])) % nz, (y + int(c[1])) % ny, (x + int(c[0])) % nx)
+        zz = z + int(c[2]) if self.walls else (z + int(c[2])) % nz
+        return (zz, (y + int(c[1])) % ny, (x + int(c[0])) % nx)
 
 
 def _normalized(v):

@@ -65,21 +65,25 @@ def _compare(cfg, st, tag):
 
 
 WALL_CASES = [
-    ("B", 1, False, (0.0, -1e-3, 0.0), (0.4, -0.3)),
-    ("A", 2, True, (1e-3, 0.0, 0.0), (-0.6, 0.2)),
-    ("B", 1, True, (0.0, 0.0, 0.0), (0.0, 0.0)),
+    ("D2Q9", (6, 5, 1), "B", 1, False, (0.0, -1e-3, 0.0), (0.4, -0.3)),
+    ("D2Q9", (6, 5, 1), "A", 2, True, (1e-3, 0.0, 0.0), (-0.6, 0.2)),
+    ("D2Q9", (6, 5, 1), "B", 1, True, (0.0, 0.0, 0.0), (0.0, 0.0)),
+    ("D3Q19", (4, 3, 5), "B", 1, False, (0.0, 0.0, -1e-3), (0.3, -0.5)),
+    ("D3Q19", (3, 4, 4), "A", 1, True, (1e-3, 0.0, 0.0), (-0.2, 0.4)),
 ]
 
 
-@pytest.mark.parametrize("model,n_exp,solve_all,grav,cos_pN", WALL_CASES)
-def test_loops_match_vectorised_walls(model, n_exp, solve_all, grav, cos_pN):
-    """Walls below y = 0 and above y = ny - 1 (half-way bounce-back, wetting ghosts)."""
+@pytest.mark.parametrize("lattice,dims,model,n_exp,solve_all,grav,cos_pN", WALL_CASES)
+def test_loops_match_vectorised_walls(lattice, dims, model, n_exp, solve_all, grav, cos_pN):
+    """Walls at both ends of the slowest axis (y in 2D, z in 3D): half-way bounce-back and
+    wetting ghosts."""
     N = 3
+    nx, ny, nz = dims
     sigma = inputs.random_sigma(N, np.random.default_rng(12), 0.005, 0.02)
-    cfg = inputs.base_cfg("D2Q9", 6, 5, 1, N, sigma, rho=[1.0, 2.5, 0.7],
+    cfg = inputs.base_cfg(lattice, nx, ny, nz, N, sigma, rho=[1.0, 2.5, 0.7],
                           tau_g=[0.8, 0.6, 1.1], mobility=0.03, eps=3.0, model=model,
                           model_a_n=n_exp, solve_all=solve_all, gravity=grav)
     cfg["walls"] = True
     cfg["contact_cos"] = list(cos_pN)
-    st = _state(cfg, seed=29 + n_exp)
-    _compare(cfg, st, f"walls {model}")
+    st = _state(cfg, seed=29 + n_exp + nz)
+    _compare(cfg, st, f"walls {lattice} {model}")

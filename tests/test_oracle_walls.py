@@ -126,40 +126,73 @@ def test_walls_conserve_mass_and_mirror_symmetry():
     assert np.abs(u[1] + u[1][::-1, :]).max() <= 1e-8 * scale_u
 
 
-def test_no_slip_layered_channel():
+def test_walls_3d_conserve_mass_and_mirror_symmetry():
+    """D3Q19 with walls below z = 0 and above z = nz - 1: per-phase mass kept, and a state
+    symmetric about the mid plane stays symmetric (phi, u_x, u_y even; u_z odd)."""
+    n, nz, N, eps = 12, 14, 3, 3.0
+    sig = inputs.random_sigma(N, np.random.default_rng(4), 0.005, 0.02)
+    cfg = inputs.base_cfg("D3Q19", n, n, nz, N, sig, [2.0, 3.0, 1.0], [0.8, 0.7, 0.9],
+                          mobility=0.05, eps=eps, model="B")
+    C = O.Config(_walled(cfg, [0.4, -0.3]))
+    balls = []
+    for (c, r, ph) in (((4.0, 5.0, 3.0), 3.0, 0), ((8.0, 7.0, 5.0), 2.5, 1)):
+        balls.append((c, r, ph))
+        balls.append(((c[0], c[1], nz - 1 - c[2]), r, ph))
+    phi0 = inputs.balls_to_phases((n, n, nz), N, balls, eps)
+    st = O.init(C, phi0)
+    m0 = O.mass(C, st)
+    st = O.step(C, st, 60)
+    m1 = O.mass(C, st)
+    assert np.abs(m1 - m0).max() <= 1e-12 * m0.max()
+    phi, u, P = O.fields(C, st)
+    scale_u = np.abs(u).max()
+    assert scale_u > 1e-7
+    assert np.abs(phi - phi[:, ::-1]).max() <= 1e-10
+    assert np.abs(u[0] - u[0][::-1]).max() <= 1e-8 * scale_u
+    assert np.abs(u[1] - u[1][::-1]).max() <= 1e-8 * scale_u
+    assert np.abs(u[2] + u[2][::-1]).max() <= 1e-8 * scale_u
+
+
+@pytest.mark.parametrize("lattice", ["D2Q9", "D3Q19"])
+def test_no_slip_layered_channel(lattice):
     """Two layers between walls (heavy below), gravity along x: the force (rho - rho_bar) g
     drives the layers in opposite directions.  The steady profile must match the
     finite-difference solution of mu u'' = -f with u = 0 half-way behind each wall
     (u_{-1} = -u_0).  Half-way bounce-back puts the no-slip point there only up to a
     relaxation-time dependent O(dx^2) offset, i.e. O(1/H^2) of the profile: 5 % at H = 16.
     A free-slip or periodic boundary misses by O(1)."""
-    nx, ny, eps, mu = 4, 16, 3.0, 0.2
+    n_w, eps, mu = 16, 3.0, 0.2
     rho = [2.0, 1.0]
     tau = [0.5 + 3.0 * mu / r for r in rho]       # equal dynamic viscosity in both layers
     g = 1e-5
-    cfg = inputs.base_cfg("D2Q9", nx, ny, 1, 2, [[0, 0.01], [0.01, 0]], rho, tau,
+    if lattice == "D2Q9":
+        nx, ny, nz = 4, n_w, 1
+    else:
+        nx, ny, nz = 2, 2, n_w
+    cfg = inputs.base_cfg(lattice, nx, ny, nz, 2, [[0, 0.01], [0.01, 0]], rho, tau,
                           mobility=0.05, eps=eps, model="B", gravity=(g, 0.0, 0.0))
     C = O.Config(_walled(cfg, [0.0]))
-    y = np.arange(ny, dtype=float)
-    p1 = 0.5 + 0.5 * np.tanh(2.0 * (ny / 2 - 0.5 - y) / eps)
-    p1 = np.repeat(p1[:, None], nx, axis=1)
+    h = np.arange(n_w, dtype=float)
+    prof = 0.5 + 0.5 * np.tanh(2.0 * (n_w / 2 - 0.5 - h) / eps)
+    p1 = np.broadcast_to(prof.reshape((n_w,) + (1,) * (len(C.shape) - 1)), C.shape).copy()
     st = O.init(C, np.stack([p1, 1 - p1]))
     st = O.step(C, st, 2500)
     phi, u, _ = O.fields(C, st)
-    f = ((C.rho[0] * phi[0] + C.rho[1] * phi[1]) - st["rho_bar"])[:, 0] * g
-    A = np.zeros((ny, ny))
-    for j in range(ny):
-        A[j, j] = -2.0 - (1.0 if j in (0, ny - 1) else 0.0)
+    line = (slice(None),) + (0,) * (len(C.shape) - 1)
+    f = ((C.rho[0] * phi[0] + C.rho[1] * phi[1]) - st["rho_bar"])[line] * g
+    A = np.zeros((n_w, n_w))
+    for j in range(n_w):
+        A[j, j] = -2.0 - (1.0 if j in (0, n_w - 1) else 0.0)
         if j > 0:
             A[j, j - 1] = 1.0
-        if j < ny - 1:
+        if j < n_w - 1:
             A[j, j + 1] = 1.0
     ufd = np.linalg.solve(A, -f / mu)
-    ux = u[0][:, 0]
+    ux = u[0][line]
     scale = np.abs(ufd).max()
     assert np.abs(ux - ufd).max() <= 0.05 * scale
-    assert np.abs(u[0] - u[0][:, :1]).max() <= 1e-12 * scale   # x-invariant
-    assert np.abs(u[1]).max() <= 1e-2 * scale   # only decaying pressure waves cross it
+    assert np.abs(u[0] - ux.reshape((n_w,) + (1,) * (len(C.shape) - 1))).max() <= 1e-12 * scale
+    assert np.abs(u[-1]).max() <= 1e-2 * scale   # only decaying pressure waves cross it
 
 
 def _drop_angle(p1):
