@@ -14,9 +14,10 @@
  *   - isotropic lattice-weight gradient/Laplacian stencils, lagged velocity in the force
  *     and explicit Euler time derivatives (Sec. 3 closing paragraph).
  * Lattices: D2Q9 (the paper's) and D3Q19 (raw-moment basis built the same way).
- * Boundaries: periodic in every direction, or (D2Q9) solid walls below y = 0 and above
- * y = ny - 1 with x periodic: half-way bounce-back for the no-flux phase field and the
- * no-slip flow (Sec. 4 intro) and the N-phase wetting condition with Young's relation
+ * Boundaries: periodic in every direction, or solid walls at both ends of the slowest
+ * axis (below y = 0 and above y = ny - 1 on D2Q9, below z = 0 and above z = nz - 1 on
+ * D3Q19) with the other axes periodic: half-way bounce-back for the no-flux phase field and
+ * the no-slip flow (Sec. 4 intro) and the N-phase wetting condition with Young's relation
  * (Sec. 4.2).
  *
  * Conventions
@@ -88,11 +89,13 @@ typedef struct {
   double mobility;       /* M > 0; phase-field relaxation tau_f = 1/2 + M / c_s^2 (Sec. 3) */
   double eps;            /* interface thickness epsilon > 0 (Sec. 2.1)                     */
   double gravity[3];     /* body force (rho - rho_bar) g, rho_bar = mean density at t = 0 */
-  int32_t walls;         /* 0: periodic.  1 (D2Q9 only, ny >= 2): walls half-way below row 0
-                            and above row ny - 1.  Populations that would stream in from a
+  int32_t walls;         /* 0: periodic.  1: walls half-way before the first and after the
+                            last plane of the slowest axis (rows y = 0, ny - 1 of D2Q9,
+                            planes z = 0, nz - 1 of D3Q19; at least two planes between
+                            them).  Populations that would stream in from a
                             wall are the node's own post-collision populations of the
                             opposite direction.  The gradient and Laplacian stencils read a
-                            ghost row behind each wall: phi_p(ghost) = phi_p + (4/eps)
+                            ghost plane behind each wall: phi_p(ghost) = phi_p + (4/eps)
                             sum_{q != p} phi_p phi_q cos theta_pq at the adjacent fluid node
                             (the wetting condition n_w . grad phi_p = (4/eps) sum phi_p phi_q
                             cos theta_pq with n_w pointing into the wall, one-sided), Model B
@@ -117,8 +120,7 @@ int nphase_lbm_workspace_bytes(const nphase_lbm_params *params, size_t *bytes_ho
 
 /* Validate and copy the parameters, carve the caller's workspace and bind the stream.
  * Errors: EINVAL (bad parameters, NULL pointers, misaligned workspace), ENOMEM
- * (ws_bytes too small), ENOTSUP (N outside 2..6, walls on D3Q19).  No device work is
- * done. */
+ * (ws_bytes too small), ENOTSUP (N outside 2..6).  No device work is done. */
 int nphase_lbm_create(const nphase_lbm_params *params, void *workspace_dev, size_t ws_bytes,
                       void *hip_stream, nphase_lbm_t *out_host);
 

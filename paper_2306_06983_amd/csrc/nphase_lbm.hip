@@ -121,17 +121,14 @@ int validate(const nphase_lbm_params* p, std::string* why) {
     if (!std::isfinite(p->gravity[d])) return bad("gravity not finite");
   if (p->walls != 0 && p->walls != 1) return bad("walls must be 0 or 1");
   if (p->walls) {
-    if (p->ny < 2) return bad("walls need ny >= 2");
+    if ((p->lattice == NPHASE_D2Q9 ? p->ny : p->nz) < 2)
+      return bad("walls need at least two planes between them (ny, or nz for D3Q19)");
     for (int i = 0; i + 1 < N; ++i)
       if (!(p->contact_cos[i] >= -1.0 && p->contact_cos[i] <= 1.0))
         return bad("contact_cos must lie in [-1, 1]");
   }
   if (N < NMIN || N > NMAX) {
     if (why) *why = "n_phases outside the instantiated range [2, 6]";
-    return NPHASE_ENOTSUP;
-  }
-  if (p->walls && p->lattice != NPHASE_D2Q9) {
-    if (why) *why = "walls are built for D2Q9 only";
     return NPHASE_ENOTSUP;
   }
   return NPHASE_OK;

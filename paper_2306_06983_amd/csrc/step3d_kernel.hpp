@@ -35,6 +35,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "lattice.hpp"
 #include "step_kernel.hpp"
 
@@ -156,6 +158,10 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) nphase_momen
       store_plane(z + 1);   // its slot (plane z - 2) was last read before the previous barrier
       __syncthreads();
       if (z + 1 < zend) fetch_plane(p, z + 2);   // in flight during the compute of plane z
+      // a plane next to a wall (walls before z = 0 and after z = nz - 1) pulls the
+      // populations that would come from behind the wall from its own node, reversed
+      // (half-way bounce-back)
+      const bool wlo = a.walls && z == 0, whi = a.walls && z == nz - 1;
       if (valid) {
         const size_t gi = col + plane * z;
         const T ph_own = s_mr[slot(z)][MR<T>::PHI][rown];
@@ -170,14 +176,23 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) nphase_momen
             if constexpr (DEV) fi = LD(p * NMR + MR<T>::RES, gi);   // the rest carries the residual
             else fi = T(L::w(0)) * ph_own;
           } else {
-            const int sl = slot(z - L::c(i, 2));
-            const int rs = rown - L::c(i, 0) - RX * L::c(i, 1);
+            int sl = slot(z - L::c(i, 2));
+            int rs = rown - L::c(i, 0) - RX * L::c(i, 1);
+            bool bb = false;
+            if (L::c(i, 2) != 0) {
+              bb = L::c(i, 2) == 1 ? wlo : whi;
+              if (bb) {
+                sl = slot(z);
+                rs = rown;
+              }
+            }
             T cA = T(0), cD = T(0);
 #pragma unroll
             for (int d = 0; d < D; ++d) {
               if (L::c(i, d) == 1) cA += s_mr[sl][MR<T>::A + d][rs];
               if (L::c(i, d) == -1) cA -= s_mr[sl][MR<T>::A + d][rs];
             }
+            if (bb) cA = -cA;
             const T phs = s_mr[sl][MR<T>::PHI][rs];
             // FP32: deviation from the rest weights of the node's own phi^{t-1}
             if constexpr (DEV) fi = T(L::w(i)) * ((phs - ph_own) + cA);
@@ -188,6 +203,7 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) nphase_momen
                 if (L::c(i, d) == 1) cD += s_mr[sl][MR<T>::DD + d][rs];
                 if (L::c(i, d) == -1) cD -= s_mr[sl][MR<T>::DD + d][rs];
               }
+              if (bb) cD = -cD;
               fi += T(0.5) * cD;
             }
           }
@@ -304,11 +320,29 @@ __global__ void __launch_bounds__(NTHREADS, 2) nphase_step3d_kernel(const StepAr
   };
 
   // ---- S1: phi (+ pair fractions) of one region-plane node of plane z
-  auto s1_node = [&](int r, long long col, int z) {
-    const unsigned gi = (unsigned)(col + plane * wrap(z, nz));
+  auto s1_node = [&](int r, long long col, int z, auto wall) __attribute__((always_inline)) {
+    constexpr bool W = decltype(wall)::value;
     const int sl = ring_of(z, PHR);
+    if (W && (z < 0 || z >= nz)) {
+      // behind a wall: the wetting condition from the facing plane of fluid nodes
+      const unsigned gi = (unsigned)(col + plane * (z < 0 ? 0 : nz - 1));
+      T ph[N], gh[N];
 #pragma unroll
-    for (int p = 0; p < NS; ++p) s_phi[p][sl][r] = LD(a.mo, p, gi);
+      for (int p = 0; p < NS; ++p) ph[p] = LD(a.mo, p, gi);
+      if constexpr (!SA) {
+        T rest = ph[0];
+#pragma unroll
+        for (int p = 1; p < NS; ++p) rest += ph[p];
+        ph[N - 1] = T(1) - rest;
+      }
+      wetting_ghost<T, N>(a, ph, gh);
+#pragma unroll
+      for (int p = 0; p < NS; ++p) s_phi[p][sl][r] = gh[p];
+    } else {
+      const unsigned gi = (unsigned)(col + plane * wrap(z, nz));
+#pragma unroll
+      for (int p = 0; p < NS; ++p) s_phi[p][sl][r] = LD(a.mo, p, gi);
+    }
     if constexpr (PF_LDS) {
       T ph[N];
       phi_at(r, z, ph);
@@ -319,13 +353,13 @@ __global__ void __launch_bounds__(NTHREADS, 2) nphase_step3d_kernel(const StepAr
         for (int q = p + 1; q < N; ++q, ++k) s_pf[k][ring_of(z, 3)][r] = pair_fraction(ph[p], ph[q]);
     }
   };
-  auto s1_plane = [&](int z) {
-    s1_node(rown, col_own, z);
+  auto s1_plane = [&](int z, auto wall) __attribute__((always_inline)) {
+    s1_node(rown, col_own, z, wall);
     constexpr int NRING = RP - NTHREADS;
     for (int k = t; k < NRING; k += NTHREADS) {
       int rx, ry, rz;
       ring_coord<2, RX, RY, 1>(k, rx, ry, rz);
-      s1_node(rx + RX * ry, col_of(rx, ry), z);
+      s1_node(rx + RX * ry, col_of(rx, ry), z, wall);
     }
   };
 
@@ -449,6 +483,10 @@ __global__ void __launch_bounds__(NTHREADS, 2) nphase_step3d_kernel(const StepAr
   T Fsn[D], grn[D], Rn[NS][D], mpn[D];   // newest (plane zs2)
   T Fsc[D], grc[D], Rc[NS][D], mpc[D];   // current (plane zs3)
 
+  // the march, compiled with and without the wall branches (walls before z = 0 and after
+  // z = nz - 1), so that periodic boxes run the plain code
+  auto march = [&](auto wall) __attribute__((always_inline)) {
+  constexpr bool W = decltype(wall)::value;
   for (int k = 0; k <= (zend - z0) + 3; ++k) {
     const int zs1 = z0 - 2 + k;
     const int zs2 = zs1 - 1;
@@ -456,7 +494,7 @@ __global__ void __launch_bounds__(NTHREADS, 2) nphase_step3d_kernel(const StepAr
     // with a 3-plane phi ring this S1 overwrites the plane the previous S3 read
     if constexpr (PHR < 4) __syncthreads();
     // S1 (planes z0-2 .. zend+1)
-    if (zs1 <= zend + 1) s1_plane(zs1);
+    if (zs1 <= zend + 1) s1_plane(zs1, wall);
     __syncthreads();
     // hand the previous S2 results to S3
 #pragma unroll
@@ -530,10 +568,17 @@ __global__ void __launch_bounds__(NTHREADS, 2) nphase_step3d_kernel(const StepAr
 #pragma unroll
       for (int i = 1; i < Q; ++i) {
         const T wg = T(3) * T(L::w(i));
-        const int sl = ring_of(zs3 + L::c(i, 2), WR);
+        // behind a wall the tensor is the odd reflection of the facing fluid plane's
+        int zw = zs3 + L::c(i, 2);
+        T sg = T(1);
+        if (W && (zw < 0 || zw >= nz)) {
+          zw = zs3;
+          sg = T(-1);
+        }
+        const int sl = ring_of(zw, WR);
 #pragma unroll
         for (int kk = 0; kk < 3; ++kk) {
-          const T v = s_w[kk][sl][iown + ioff2(i)];
+          const T v = sg * s_w[kk][sl][iown + ioff2(i)];
 #pragma unroll
           for (int d = 0; d < D; ++d) {
             if (L::c(i, d) == 1) DW[kk][d] += wg * v;
@@ -631,6 +676,7 @@ __global__ void __launch_bounds__(NTHREADS, 2) nphase_step3d_kernel(const StepAr
         return (unsigned)X[L::c(i, 0) + 1] +
                (unsigned)nx * ((unsigned)Y[L::c(i, 1) + 1] + (unsigned)ny * (unsigned)Z[L::c(i, 2) + 1]);
       };
+      const bool wall_lo = W && zs3 == 0, wall_hi = W && zs3 == nz - 1;
 #pragma unroll
       for (int p = 0; p < NS; ++p) {
         const T ph = phi_own[p];
@@ -710,7 +756,10 @@ __global__ void __launch_bounds__(NTHREADS, 2) nphase_step3d_kernel(const StepAr
               if (L::c(i, d) != 0 && L::c(i, e) != 0)
                 corr = T(0.25) * T(L::c(i, d) * L::c(i, e)) * Nn[d][e];
         }
-        ST(a.g_dst, i - 1, dest(i), geq + T(0.5) * Fi + oms2 * corr);
+        // toward a wall: bounce-back into the opposite direction at the own node
+        const bool bb = (L::c(i, 2) == -1 && wall_lo) || (L::c(i, 2) == 1 && wall_hi);
+        ST(a.g_dst, bb ? opposite<L>(i) - 1 : i - 1, bb ? g_own : dest(i),
+           geq + T(0.5) * Fi + oms2 * corr);
       }
 #pragma unroll
       for (int d = 0; d < D; ++d) {
@@ -719,6 +768,9 @@ __global__ void __launch_bounds__(NTHREADS, 2) nphase_step3d_kernel(const StepAr
       }
     }
   }
+  };
+  if (a.walls) march(std::true_type{});
+  else march(std::false_type{});
 }
 
 // ---- moment-representation state outside the step ----------------------------------------
@@ -811,9 +863,10 @@ __global__ void __launch_bounds__(256)
       } else {
         const int xs = (x - L::c(i, 0) + nx) % nx, ys = (y - L::c(i, 1) + ny) % ny;
         const int zs = (z - L::c(i, 2) + nz) % nz;
-        // behind a wall (rows -1 and ny): half-way bounce-back, the node's own population
-        // of the opposite direction
-        const bool bb = walls && (y - L::c(i, 1) < 0 || y - L::c(i, 1) >= ny);
+        // behind a wall (index -1 or n of the slowest axis: y in 2D, z in 3D): half-way
+        // bounce-back, the node's own population of the opposite direction
+        const int hw = D == 2 ? y : z, nw = D == 2 ? ny : nz;
+        const bool bb = walls && (hw - L::c(i, D - 1) < 0 || hw - L::c(i, D - 1) >= nw);
         const long long sn = bb ? gl : xs + (long long)nx * (ys + (long long)ny * zs);
         const double sg = bb ? -1.0 : 1.0;
         double cA = 0.0, cD = 0.0;

@@ -83,7 +83,8 @@ struct StepArgs {
   T four_over_eps;        // 4 / eps
   T rho_bar;
   T grav[3];
-  int walls;   // D2Q9: 1 = walls half-way below row 0 and above row ny - 1 (x periodic)
+  int walls;   // 1 = walls half-way before the first and after the last plane of the
+               // slowest axis (rows y of D2Q9, planes z of D3Q19); other axes periodic
   // per unordered pair p < q: (4 / eps) cos theta_pq (cos theta_qp = -cos theta_pq)
   T wet[MAXN * (MAXN - 1) / 2];
 };
@@ -206,6 +207,30 @@ __device__ __forceinline__ void chemical_potentials(const A& a, const T* ph, con
       mu[q] += b * (gp[q] - gpq) - kk * lap[p];
     }
   }
+}
+
+// Ghost values behind a wall from the N order parameters ph of the facing fluid node: the
+// wetting condition of Sec. 4.2, n_w . grad phi_p = sum_{q != p} (4/eps) phi_p phi_q
+// cos theta_pq with n_w pointing into the wall, taken one-sided across the half-way wall:
+// out_p = phi_p + sum_{q != p} (4/eps) cos theta_pq phi_p phi_q (a.wet holds (4/eps) cos
+// theta_pq per pair p < q; cos theta_qp = -cos theta_pq).
+template <typename T, int N, typename A>
+__device__ __forceinline__ void wetting_ghost(const A& a, const T* ph, T* out) {
+  T acc[N];
+#pragma unroll
+  for (int p = 0; p < N; ++p) acc[p] = T(0);
+  int k = 0;
+#pragma unroll
+  for (int p = 0; p < N; ++p) {
+#pragma unroll
+    for (int q = p + 1; q < N; ++q, ++k) {
+      const T v = a.wet[k] * ph[p] * ph[q];
+      acc[p] += v;
+      acc[q] -= v;
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < N; ++p) out[p] = ph[p] + acc[p];
 }
 
 // Moment form of the post-collision populations of one evolved set (the state the step
@@ -453,21 +478,10 @@ __global__ void __launch_bounds__((StepTile<T, LAT, N, SA, MODEL>::NT),
           for (int p = 1; p < NS; ++p) rest += ph[p];
           ph[N - 1] = T(1) - rest;
         }
-        T acc[N];
+        T gh[N];
+        wetting_ghost<T, N>(a, ph, gh);
 #pragma unroll
-        for (int p = 0; p < N; ++p) acc[p] = T(0);
-        int kk = 0;
-#pragma unroll
-        for (int p = 0; p < N; ++p) {
-#pragma unroll
-          for (int q = p + 1; q < N; ++q, ++kk) {
-            const T v = a.wet[kk] * ph[p] * ph[q];
-            acc[p] += v;
-            acc[q] -= v;
-          }
-        }
-#pragma unroll
-        for (int p = 0; p < NS; ++p) s_phi[p][rx + RX * ry] = ph[p] + acc[p];
+        for (int p = 0; p < NS; ++p) s_phi[p][rx + RX * ry] = gh[p];
       }
       __syncthreads();
     }

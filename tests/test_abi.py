@@ -101,13 +101,18 @@ def test_unsupported_phase_count(lib):
     assert rc == B.NPHASE_ENOTSUP
 
 
-def test_walls_d3q19_unsupported(lib):
+def test_walls_need_two_planes(lib):
+    """Walls sit before the first and after the last plane of the slowest axis (y on D2Q9,
+    z on D3Q19): at least two planes between them."""
     cfg = inputs.base_cfg("D3Q19", 16, 16, 16, 3, inputs.uniform_sigma(3, 0.01), [1.0] * 3,
                           [0.8] * 3)
     cfg["walls"] = True
     rc, _ = _ws(lib, B.make_params(cfg))
-    assert rc == B.NPHASE_ENOTSUP
-    cfg["lattice"], cfg["nz"] = "D2Q9", 1
+    assert rc == B.NPHASE_OK
+    cfg["nz"] = 1
+    rc, _ = _ws(lib, B.make_params(cfg))
+    assert rc == B.NPHASE_EINVAL
+    cfg["lattice"], cfg["nz"], cfg["ny"] = "D2Q9", 1, 2
     rc, _ = _ws(lib, B.make_params(cfg))
     assert rc == B.NPHASE_OK
 

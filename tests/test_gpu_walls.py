@@ -1,19 +1,21 @@
-"""GPU parity with walls (D2Q9): half-way bounce-back below row 0 and above row ny - 1 and
-the N-phase wetting condition with Young's relation, through the C ABI, against the FP64
-oracle on the same seeded inputs.
+"""GPU parity with walls: half-way bounce-back at both ends of the slowest axis (below row 0
+and above row ny - 1 on D2Q9, below plane 0 and above plane nz - 1 on D3Q19) and the N-phase
+wetting condition with Young's relation, through the C ABI, against the FP64 oracle on the
+same seeded inputs.
 
 Bars (as for the periodic box): FP64 max |dphi| <= 1e-12 and max |du| / max |u|,
 max |dP| / max |P| <= 1e-12; FP64 mass conserved to 1e-12; FP32 max |dphi| <= 2e-5 and
 per-phase relative mass drift <= 1e-6.  The FP64 export of the state (save_state64) must
 equal the oracle's post-stream populations, the bounced-back ones at the walls included.
 Grids are ragged (ny not a multiple of the 8-row tile, so a tile holds rows past the top
-wall) or tile-exact, down to ny = 2 where both walls touch the same tile row pair."""
+wall; nz not a multiple of the 32-plane run) or tile-exact, down to ny = 2 where both walls
+touch the same tile row pair."""
 import math
 
 import numpy as np
 import pytest
 
-from _helpers import errors, ragged_discs, run_gpu, run_oracle
+from _helpers import errors, ragged_discs, ragged_spheres, run_gpu, run_oracle
 from paper_2306_06983_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -56,6 +58,21 @@ def _discs(*args, cos_pN, **kw):
     return _walled(cfg, cos_pN), phi
 
 
+def _spheres(*args, cos_pN, **kw):
+    cfg, phi = ragged_spheres(*args, **kw)
+    return _walled(cfg, cos_pN), phi
+
+
+def _cap_3d(n=16, nz=12):
+    """A half-sphere R = 6 of phase 0 on the bottom wall (z = -1/2), phase 1 around it."""
+    z, y, x = np.mgrid[0:nz, 0:n, 0:n].astype(float)
+    r = np.sqrt((x - n / 2 + 0.5) ** 2 + (y - n / 2 + 0.5) ** 2 + (z + 0.5) ** 2)
+    p1 = 0.5 + 0.5 * np.tanh(2.0 * (6.0 - r) / 3.0)
+    cfg = inputs.base_cfg("D3Q19", n, n, nz, 2, [[0, 0.01], [0.01, 0]], [2.0, 1.0],
+                          [0.8, 0.8], mobility=0.1, eps=3.0, model="B")
+    return _walled(cfg, [math.cos(math.radians(60.0))]), np.stack([p1, 1 - p1])
+
+
 CASES = {
     "walls_B_N3_50x37": (lambda: _discs(50, 37, cos_pN=[0.4, -0.3]), 200),
     "walls_A2_N4_solve_all_gravity_45x33": (
@@ -65,6 +82,11 @@ CASES = {
     "walls_A1_N3_33x9": (lambda: _discs(33, 9, model="A", count=2, rmin=2.5, rmax=3.5,
                                         cos_pN=[-0.2, 0.6]), 120),
     "walls_B_N3_mixture_7x2": (lambda: _random_mixture(7, 2), 40),
+    "walls3d_B_N4_21x17x19": (lambda: _spheres(21, 17, 19, cos_pN=[0.4, -0.3, 0.2]), 30),
+    "walls3d_A2_N3_solve_all_gravity_18x14x37": (
+        lambda: _spheres(18, 14, 37, N=3, model="A", model_a_n=2, solve_all=True,
+                         gravity=(0.0, 0.0, -1e-5), cos_pN=[-0.5, 0.3]), 25),
+    "walls3d_B_N2_cap_16x16x12": (lambda: _cap_3d(), 30),
 }
 
 
@@ -107,17 +129,18 @@ def test_walls_state64_matches_oracle_populations(case):
     import torch
     from paper_2306_06983_amd import binding as B
     name, cfg, phi, steps, o = case
-    nx, ny, N = cfg["nx"], cfg["ny"], cfg["n_phases"]
+    N = cfg["n_phases"]
     NS = N if cfg.get("solve_all", False) else N - 1
-    V, Q = nx * ny, 9
+    grid = tuple(phi.shape[1:])
+    V, Q = int(np.prod(grid)), (9 if cfg["lattice"] == "D2Q9" else 19)
     s = B.Sim(cfg, "fp64").init(phi)
     s.step(steps)
     buf = s.save_state64()
     torch.cuda.synchronize()
     pay = buf[HDR:].view(torch.float64).cpu().numpy()
     s.close()
-    f = pay[:NS * Q * V].reshape(NS, Q, ny, nx)
-    g = pay[NS * Q * V:NS * Q * V + (Q - 1) * V].reshape(Q - 1, ny, nx)
+    f = pay[:NS * Q * V].reshape((NS, Q) + grid)
+    g = pay[NS * Q * V:NS * Q * V + (Q - 1) * V].reshape((Q - 1,) + grid)
     st = o["state"]
     ef = np.abs(f - st["f"]).max() / np.abs(st["f"]).max()
     eg = np.abs(g - st["g"][1:]).max() / max(np.abs(st["g"][1:]).max(), 1e-300)
