@@ -13,7 +13,7 @@ workload description that calls the ambient "phase 1" is therefore stored in the
 cfg dictionary keys (shared with the oracle and the binding):
   lattice ('D2Q9'|'D3Q19'), nx, ny, nz, n_phases, sigma (N x N nested list), rho (N),
   tau_g (N), mobility, eps, model ('A'|'B'), model_a_n, solve_all, gravity (3 floats),
-  and optionally walls (bool, D2Q9: walls below row 0 and above row ny - 1) and
+  and optionally walls (bool: walls at both ends of the slowest axis, rows of D2Q9, z planes of D3Q19) and
   contact_cos (N-1 floats, cos theta_pN).
 """
 import math
