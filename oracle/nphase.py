@@ -29,7 +29,9 @@ Readings where the paper is silent (each listed in the design notes of the repos
   * normals use n = G/|G| if |G|^2 > NORMAL_EPS^2 else 0;
   * Model B pairwise fraction phi_pq = phi_p/(phi_p+phi_q) if phi_p+phi_q > PAIR_EPS else
     1/2, its gradient is the isotropic stencil applied to the phi_pq field, and
-    n_qp := -n_pq;
+    n_qp := -n_pq; or, as an option (pair_normals = "chain"), the direction of the chain
+    rule of Sec. 2.1, grad phi_pq = (phi_q grad phi_p - phi_p grad phi_q)/(phi_p+phi_q)^2,
+    from the phase gradients: n_pq = normalize(phi_q G_p - phi_p G_q);
   * the reconstructed phase phi_N = 1 - sum(solved) is a field like the others (its
     gradient, Laplacian, source and chemical potential use the same formulas);
   * div(m_phi u - u m_phi) contracts the first index: F_c,b = -1/2 d_a(m_a u_b - u_a m_b),
@@ -87,6 +89,8 @@ class Config:
         self.model = cfg["model"]
         self.model_a_n = int(cfg.get("model_a_n", 1))
         self.solve_all = bool(cfg.get("solve_all", False))
+        self.pair_normals = cfg.get("pair_normals", "stencil")
+        assert self.pair_normals in ("stencil", "chain")
         self.gravity = np.array(list(cfg.get("gravity", [0.0, 0.0, 0.0]))[:d], dtype=np.float64)
         # Sec. 2.2: beta_pq = 3 sigma_pq / eps, k_pq = -3 eps sigma_pq / 4
         self.beta = 3.0 * self.sigma / self.eps
@@ -254,20 +258,25 @@ def pair_fraction(a, b):
     return np.where(ok, a / np.where(ok, s, 1.0), 0.5)
 
 
-def source_model_b(phi, C, ghost=None):
+def source_model_b(phi, C, ghost=None, G=None):
     """Eq. (eq-source2): R_p = sum_{q != p} 4 phi_p phi_q / eps * n_pq with
-    n_pq = grad(phi_pq)/|grad(phi_pq)| and phi_pq = phi_p / (phi_p + phi_q)."""
+    n_pq = grad(phi_pq)/|grad(phi_pq)| and phi_pq = phi_p / (phi_p + phi_q).  With
+    C.pair_normals == "chain" the direction is taken from the chain rule of Sec. 2.1 on the
+    phase gradients G: n_pq = normalize(phi_q G_p - phi_p G_q)."""
     lat = C.lat
     N = phi.shape[0]
     R = np.zeros((N, lat.d) + phi.shape[1:])
     for p in range(N):
         for q in range(p + 1, N):
-            phi_pq = pair_fraction(phi[p], phi[q])
-            gpq = None
-            if ghost is not None:
-                gpq = (pair_fraction(ghost[0][p], ghost[0][q]),
-                       pair_fraction(ghost[1][p], ghost[1][q]))
-            n_pq = _normalize(grad(phi_pq, lat, gpq))
+            if C.pair_normals == "chain":
+                n_pq = _normalize(phi[q][None] * G[p] - phi[p][None] * G[q])
+            else:
+                phi_pq = pair_fraction(phi[p], phi[q])
+                gpq = None
+                if ghost is not None:
+                    gpq = (pair_fraction(ghost[0][p], ghost[0][q]),
+                           pair_fraction(ghost[1][p], ghost[1][q]))
+                n_pq = _normalize(grad(phi_pq, lat, gpq))
             coef = 4.0 * phi[p] * phi[q] / C.eps
             R[p] = R[p] + coef * n_pq
             R[q] = R[q] + coef * (-n_pq)
@@ -367,7 +376,7 @@ def macroscopic(C, state):
     if C.model == "A":
         R = source_model_a(phi, G, C)
     else:
-        R = source_model_b(phi, C, gh)
+        R = source_model_b(phi, C, gh, G)
 
     # chemical potentials and the potential-form surface tension
     gp = [gprime(phi[p]) for p in range(C.N)]

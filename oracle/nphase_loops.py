@@ -25,7 +25,8 @@ stencils read ghost nodes behind a wall, whose order
 parameters follow from the wetting condition of Sec. 4.2 at the adjacent fluid node (wall
 normal out of the fluid, one lattice spacing, contact angles from the Sec. 4.2 Young
 relation), pair fractions from those, and the tensor m_phi u^- - u^- m_phi with its sign
-flipped (the same readings as the vectorised oracle).
+flipped (the same readings as the vectorised oracle).  The chain-rule option for the Model B
+pair normals (pair_normals = "chain") takes n_pq along phi_q grad phi_p - phi_p grad phi_q.
 """
 import itertools
 import math
@@ -59,6 +60,7 @@ class Params:
         self.mob = float(cfg["mobility"])
         self.tau_f = 0.5 + self.mob / CS2
         self.model = cfg["model"]
+        self.chain = cfg.get("pair_normals", "stencil") == "chain"
         self.n_exp = int(cfg.get("model_a_n", 1))
         grav = list(cfg.get("gravity", [0.0, 0.0, 0.0]))
         self.grav = [float(grav[a]) for a in range(self.d)]
@@ -201,7 +203,11 @@ def _one_step(P, st):
                         v = phi_g(Y)
                         s_ = v[p] + v[q]
                         return v[p] / s_ if s_ > PAIR_EPS else 0.5
-                    npq = _normalized(_grad_at(P, X, frac))
+                    if P.chain:   # direction of (phi_q grad phi_p - phi_p grad phi_q)
+                        npq = _normalized([ph[q] * G[X][p][a] - ph[p] * G[X][q][a]
+                                           for a in range(d)])
+                    else:
+                        npq = _normalized(_grad_at(P, X, frac))
                     coef = 4.0 * ph[p] * ph[q] / P.eps
                     for a in range(d):
                         Rp[p][a] += coef * npq[a]

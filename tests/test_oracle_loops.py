@@ -39,6 +39,26 @@ CASES = [
 ]
 
 
+CHAIN_CASES = [
+    ("D2Q9", (6, 6, 1), "B", 1, False, (0.0, -1e-3, 0.0)),
+    ("D3Q19", (4, 4, 3), "B", 1, True, (0.0, 0.0, 1e-3)),
+]
+
+
+@pytest.mark.parametrize("lattice,dims,model,n_exp,solve_all,grav", CHAIN_CASES)
+def test_loops_match_vectorised_chain_normals(lattice, dims, model, n_exp, solve_all, grav):
+    """The chain-rule pair normals (phi_q grad phi_p - phi_p grad phi_q) in both writings."""
+    nx, ny, nz = dims
+    N = 3
+    sigma = inputs.random_sigma(N, np.random.default_rng(13), 0.005, 0.02)
+    cfg = inputs.base_cfg(lattice, nx, ny, nz, N, sigma, rho=[1.0, 2.5, 0.7],
+                          tau_g=[0.8, 0.6, 1.1], mobility=0.03, eps=3.0, model=model,
+                          model_a_n=n_exp, solve_all=solve_all, gravity=grav)
+    cfg["pair_normals"] = "chain"
+    st = _state(cfg, seed=41 + nz)
+    _compare(cfg, st, f"chain {lattice}")
+
+
 @pytest.mark.parametrize("lattice,dims,model,n_exp,solve_all,grav", CASES)
 def test_loops_match_vectorised(lattice, dims, model, n_exp, solve_all, grav):
     nx, ny, nz = dims
