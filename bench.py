@@ -282,10 +282,12 @@ def main():
     import torch
     from paper_2306_06983_amd import inputs
 
-    def spheres(prec, steps, warm):
+    def spheres(prec, steps, warm, chain=False):
         c3, p3 = inputs.spheres(n=256)   # 256^3 D3Q19, N = 4, three drops
-        return time_extra(c3, p3, prec, steps, warm, 3, 19, c3["n_phases"] - 1,
-                          "spheres_256x256x256_N4_d3q19")
+        label = "spheres_256x256x256_N4_d3q19"
+        if chain:   # Model B with the chain-rule pair normals
+            c3, label = dict(c3, pair_normals="chain"), label + "_chain_normals"
+        return time_extra(c3, p3, prec, steps, warm, 3, 19, c3["n_phases"] - 1, label)
 
     def bands(prec, steps, warm):
         c4, p4 = inputs.layered_bands()   # 2048^2 D2Q9, N = 5 bands, gravity
@@ -315,6 +317,9 @@ def main():
     cfgA = dict(cfg, model="A", model_a_n=1)
     rA = time_gpu(cfgA, phi, "fp64", K, W)
     rA32 = time_gpu(cfgA, phi, "fp32", K, W)
+    cfgC = dict(cfg, pair_normals="chain")   # Model B, chain-rule pair normals
+    rC = time_gpu(cfgC, phi, "fp64", K, W)
+    rC32 = time_gpu(cfgC, phi, "fp32", K, W)
 
     def mlups(r):
         return V / (r["ms_per_step"] * 1e-3) / 1e6
@@ -369,11 +374,14 @@ def main():
                  "bytes_per_node_update": b32,
                  "max_abs_dphi_vs_fp64": dphi32, "mass_drift_rel": drift32},
         "model_a_n1": {"fp64_mlups": round(mlups(rA), 1), "fp32_mlups": round(mlups(rA32), 1)},
+        "model_b_chain_normals": {"fp64_mlups": round(mlups(rC), 1),
+                                  "fp32_mlups": round(mlups(rC32), 1)},
         "fp64_mass_drift_rel": drift64,
         "finite": bool(r64["finite"] and r32["finite"]),
     }
     if not args.no_extra:
         line["other_workloads"] = [spheres("fp64", 100, 10), spheres("fp32", 100, 10),
+                                   spheres("fp64", 100, 10, chain=True),
                                    bands("fp32", 500, 50), rti("fp64", 2000, 200),
                                    rti("fp32", 2000, 200)]
         line["rti_ternary_diagnostics"] = {"fp64": rti_diagnostics("fp64"),

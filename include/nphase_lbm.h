@@ -107,6 +107,14 @@ typedef struct {
                             [-1, 1]; every other pair follows Young's relation
                             cos theta_pq = (sigma_pN cos theta_pN - sigma_qN cos theta_qN) /
                             sigma_pq (Sec. 4.2).  Ignored without walls.                  */
+  int32_t pair_normals;  /* Model B pair normals n_pq.  0: the isotropic stencil applied to the
+                            pair-fraction field phi_pq = phi_p / (phi_p + phi_q) (Sec. 2.1,
+                            Eq. eq-source2).  1: the direction of the chain rule of that
+                            gradient, phi_q grad phi_p - phi_p grad phi_q (Sec. 2.1, Model B
+                            rewritten in the phase normals); identical wherever two phases
+                            are present, second-order different at triple junctions, and
+                            cheaper (no pair-fraction stencils).  Ignored for Model A.      */
+  int32_t pad1;
 } nphase_lbm_params;
 
 /* Bytes of device workspace for this parameter set: both state buffers, the reduction
@@ -196,7 +204,7 @@ int nphase_lbm_save_state64(nphase_lbm_t h, void *state64_dev);
  * the guard, pair fractions of absent pairs) are differentiated as the constants the
  * forward returns there.  The gravity reference density is treated as fixed, so these
  * entry points return NPHASE_ENOTSUP for non-zero gravity; they also return it for walls
- * (the reverse of the wall step is not built).
+ * and for the chain-rule pair normals (their reverse is not built).
  *
  * adjoint_workspace_bytes: device scratch for one adjoint step (caller-owned).
  * adjoint_seed:  adj_state = dL/ds^T for L depending on the phase fields phi(T) [N][V]

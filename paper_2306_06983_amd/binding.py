@@ -43,6 +43,8 @@ class Params(ctypes.Structure):
         ("walls", ctypes.c_int32),
         ("pad0", ctypes.c_int32),
         ("contact_cos", ctypes.c_double * MAX_N),
+        ("pair_normals", ctypes.c_int32),
+        ("pad1", ctypes.c_int32),
     ]
 
 
@@ -134,6 +136,7 @@ def make_params(cfg, precision="fp64"):
     p.walls = 1 if cfg.get("walls", False) else 0
     for i, c in enumerate(cfg.get("contact_cos", [])):
         p.contact_cos[i] = float(c)
+    p.pair_normals = {"stencil": 0, "chain": 1}[cfg.get("pair_normals", "stencil")]
     return p
 
 

@@ -120,6 +120,7 @@ int validate(const nphase_lbm_params* p, std::string* why) {
   for (int d = 0; d < 3; ++d)
     if (!std::isfinite(p->gravity[d])) return bad("gravity not finite");
   if (p->walls != 0 && p->walls != 1) return bad("walls must be 0 or 1");
+  if (p->pair_normals != 0 && p->pair_normals != 1) return bad("pair_normals must be 0 or 1");
   if (p->walls) {
     if ((p->lattice == NPHASE_D2Q9 ? p->ny : p->nz) < 2)
       return bad("walls need at least two planes between them (ny, or nz for D3Q19)");
@@ -132,6 +133,12 @@ int validate(const nphase_lbm_params* p, std::string* why) {
     return NPHASE_ENOTSUP;
   }
   return NPHASE_OK;
+}
+
+// kernel model: A, B, or B with the chain-rule pair normals
+int step_model(const nphase_lbm_params& p) {
+  if (p.model == NPHASE_MODEL_B && p.pair_normals == 1) return MODEL_BC;
+  return p.model;
 }
 
 int fail_hip(nphase_lbm_t h, hipError_t e, const char* where) {
@@ -213,7 +220,7 @@ void refresh_args(nphase_lbm_t h) {
 }
 
 hipError_t launch(nphase_lbm_t h, int mode, int side) {
-  const int N = h->N, sa = h->prm.solve_all, model = h->prm.model;
+  const int N = h->N, sa = h->prm.solve_all, model = step_model(h->prm);
   if (h->prec == NPHASE_FP64) {
     StepArgs<double> a = h->a64[side];
     a.first = h->t == 0;
@@ -375,7 +382,7 @@ int nphase_lbm_fields(nphase_lbm_t h, double* phi_dev, double* u_dev, double* p_
     a.first = h->t == 0;
     a.phi_out = sphi; a.u_out = su; a.p_out = sp;
     a.f_dst = nullptr; a.g_dst = nullptr; a.u_dst = nullptr;
-    const int N = h->N, sa = h->prm.solve_all, model = h->prm.model;
+    const int N = h->N, sa = h->prm.solve_all, model = step_model(h->prm);
     hipError_t e = h->lat == NPHASE_D2Q9
                        ? launch_step<double, LAT_D2Q9>(N, sa, model, MODE_FIELDS, a, h->ntiles, h->stream)
                        : launch_step<double, LAT_D3Q19>(N, sa, model, MODE_FIELDS, a, h->ntiles, h->stream);
@@ -385,7 +392,7 @@ int nphase_lbm_fields(nphase_lbm_t h, double* phi_dev, double* u_dev, double* p_
     a.first = h->t == 0;
     a.phi_out = sphi; a.u_out = su; a.p_out = sp;
     a.f_dst = nullptr; a.g_dst = nullptr; a.u_dst = nullptr;
-    const int N = h->N, sa = h->prm.solve_all, model = h->prm.model;
+    const int N = h->N, sa = h->prm.solve_all, model = step_model(h->prm);
     hipError_t e = h->lat == NPHASE_D2Q9
                        ? launch_step<float, LAT_D2Q9>(N, sa, model, MODE_FIELDS, a, h->ntiles, h->stream)
                        : launch_step<float, LAT_D3Q19>(N, sa, model, MODE_FIELDS, a, h->ntiles, h->stream);
@@ -665,6 +672,10 @@ int adj_check(nphase_lbm_t h) {
   }
   if (h->prm.walls) {
     h->err = "the adjoint is built for periodic boundaries only";
+    return NPHASE_ENOTSUP;
+  }
+  if (step_model(h->prm) == MODEL_BC) {
+    h->err = "the adjoint is built for the stencil pair normals of Model B only";
     return NPHASE_ENOTSUP;
   }
   return NPHASE_OK;

@@ -366,7 +366,7 @@ __global__ void __launch_bounds__(NTHREADS, 2) nphase_step3d_kernel(const StepAr
   // ---- S2 at region node r of plane z: G, R (and L when lap), m_phi; returns via refs
   auto s2_node = [&](int r, int z, bool lap, T (&G)[N][D], T (&Lp)[N], T (&R)[N][D],
                      T (&phc)[N], T (&mphi)[D]) {
-    T H[(MODEL == MODEL_B) ? NP : 1][D];
+    T H[(MODEL != MODEL_A) ? NP : 1][D];
 #pragma unroll
     for (int p = 0; p < N; ++p) {
       Lp[p] = T(0);
@@ -439,6 +439,17 @@ __global__ void __launch_bounds__(NTHREADS, 2) nphase_step3d_kernel(const StepAr
         for (int d = 0; d < D; ++d) R[p][d] = ap[p] * nv[p][d] - lam * an[d];
       }
     } else {
+      if constexpr (MODEL == MODEL_BC) {
+        // chain rule of the pair-fraction gradient (Sec. 2.1): its direction is that of
+        // phi_q grad phi_p - phi_p grad phi_q (the positive factor (phi_p + phi_q)^-2 drops)
+        int kc = 0;
+#pragma unroll
+        for (int p = 0; p < N; ++p)
+#pragma unroll
+          for (int q = p + 1; q < N; ++q, ++kc)
+#pragma unroll
+            for (int d = 0; d < D; ++d) H[kc][d] = phc[q] * G[p][d] - phc[p] * G[q][d];
+      }
 #pragma unroll
       for (int p = 0; p < N; ++p)
 #pragma unroll

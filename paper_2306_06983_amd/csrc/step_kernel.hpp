@@ -52,7 +52,8 @@ constexpr double PAIR_EPS = 1e-12;     // phi_p + phi_q > PAIR_EPS, else phi_pq 
 constexpr int MODE_STEP = 0;
 constexpr int MODE_FIELDS = 1;
 constexpr int MODEL_A = 0;
-constexpr int MODEL_B = 1;
+constexpr int MODEL_B = 1;    // pair normals from the stencil of the pair-fraction field
+constexpr int MODEL_BC = 2;   // Model B with the chain-rule pair normals
 
 template <typename T>
 struct StepArgs {
@@ -535,7 +536,7 @@ __global__ void __launch_bounds__((StepTile<T, LAT, N, SA, MODEL>::NT),
   T G[N][D], Lp[N], R[N][D], phc[N], mphi[D];
   // computes G, R (and L when lap) at region node r, then m_phi
   auto stage2 = [&](int r, bool lap) {
-    T H[(MODEL == MODEL_B) ? NP : 1][D];   // Model B: gradients of the pair fractions
+    T H[(MODEL != MODEL_A) ? NP : 1][D];   // Model B: gradients of the pair fractions
 #pragma unroll
     for (int p = 0; p < N; ++p) {
       Lp[p] = T(0);
@@ -608,6 +609,17 @@ __global__ void __launch_bounds__((StepTile<T, LAT, N, SA, MODEL>::NT),
         for (int d = 0; d < D; ++d) R[p][d] = ap[p] * nv[p][d] - lam * an[d];
       }
     } else {
+      if constexpr (MODEL == MODEL_BC) {
+        // chain rule of the pair-fraction gradient (Sec. 2.1): its direction is that of
+        // phi_q grad phi_p - phi_p grad phi_q (the positive factor (phi_p + phi_q)^-2 drops)
+        int kc = 0;
+#pragma unroll
+        for (int p = 0; p < N; ++p)
+#pragma unroll
+          for (int q = p + 1; q < N; ++q, ++kc)
+#pragma unroll
+            for (int d = 0; d < D; ++d) H[kc][d] = phc[q] * G[p][d] - phc[p] * G[q][d];
+      }
 #pragma unroll
       for (int p = 0; p < N; ++p)
 #pragma unroll
