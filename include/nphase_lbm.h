@@ -54,7 +54,7 @@ enum {
   NPHASE_EDEVICE = -3,  /* a HIP call failed                                            */
   NPHASE_ENAN = -4,     /* non-finite values found by nphase_lbm_check                  */
   NPHASE_ESTATE = -5,   /* handle in a failed state, or not initialised                 */
-  NPHASE_ENOTSUP = -6   /* valid parameters outside what this build supports            */
+  NPHASE_ENOTSUP = -6   /* valid parameters outside what the library supports          */
 };
 
 enum { NPHASE_D2Q9 = 0, NPHASE_D3Q19 = 1 };
@@ -65,7 +65,7 @@ enum { NPHASE_MODEL_A = 0, NPHASE_MODEL_B = 1 };
  *   arithmetic; the initial equilibrium set-up and the per-phase mass reductions are FP64. */
 enum { NPHASE_FP64 = 0, NPHASE_FP32 = 1 };
 
-#define NPHASE_MAX_N 8 /* size of the parameter arrays; this build evolves N in [2, 6] */
+#define NPHASE_MAX_N 8 /* size of the parameter arrays; the library evolves N in [2, 6] */
 
 typedef struct nphase_lbm_s *nphase_lbm_t;
 
@@ -74,7 +74,7 @@ typedef struct {
   int32_t struct_size;   /* = sizeof(nphase_lbm_params) (ABI check)                       */
   int32_t lattice;       /* NPHASE_D2Q9 | NPHASE_D3Q19                                    */
   int32_t nx, ny, nz;    /* grid; nz = 1 for D2Q9; every extent >= 1                      */
-  int32_t n_phases;      /* N, 2..6 in this build                                         */
+  int32_t n_phases;      /* N, 2..6 (the instantiated phase counts)                        */
   int32_t model;         /* NPHASE_MODEL_A | NPHASE_MODEL_B                               */
   int32_t model_a_n;     /* Model A exponent n (integer >= 1, Sec. 2.1); ignored for B    */
   int32_t precision;     /* NPHASE_FP64 | NPHASE_FP32                                     */

@@ -38,7 +38,7 @@ def test_compound_droplet_wetted_lengths(theta23, steps):
     degrees and theta_23 = 60 or 90 degrees; the wetted lengths L1, L2 / R must come at
     least as close to the analytical equilibrium of Table 2 as the paper's Model B run,
     plus 1 % (the run is cut at 6e6 steps, about 60 s in FP32, while the contact lines
-    still creep; M and the wall discretisation are readings).  Near 120 degrees this build
+    still creep; M and the wall discretisation are readings).  Near 120 degrees this method
     leaves L2 below the paper's value (0.45 at 6e6 steps against 0.50 of the paper), so
     that case is reported in the design notes rather than tested."""
     from paper_2306_06983_amd import binding as B
