@@ -204,7 +204,8 @@ int nphase_lbm_save_state64(nphase_lbm_t h, void *state64_dev);
  * the guard, pair fractions of absent pairs) are differentiated as the constants the
  * forward returns there.  The gravity reference density is treated as fixed, so these
  * entry points return NPHASE_ENOTSUP for non-zero gravity; they also return it for walls
- * and for the chain-rule pair normals (their reverse is not built).
+ * (the reverse of the wall step is not built).  Both kinds of Model B pair normals are
+ * differentiated.
  *
  * adjoint_workspace_bytes: device scratch for one adjoint step (caller-owned).
  * adjoint_seed:  adj_state = dL/ds^T for L depending on the phase fields phi(T) [N][V]

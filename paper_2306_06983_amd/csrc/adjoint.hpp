@@ -173,6 +173,12 @@ __global__ void __launch_bounds__(256) adj_fwd2(const AdjArgs a) {
     for (int p = 0; p < N; ++p)
       for (int d = 0; d < D; ++d) R[p][d] = ap[p] * nv[p][d] - (pw[p] / spw) * an[d];
   } else {
+    if (MODEL == MODEL_BC) {   // chain-rule pair normals: H_pq = phi_q G_p - phi_p G_q
+      int kc = 0;
+      for (int p = 0; p < N; ++p)
+        for (int q = p + 1; q < N; ++q, ++kc)
+          for (int d = 0; d < D; ++d) H[kc][d] = phc[q] * G[p][d] - phc[p] * G[q][d];
+    }
     int k = 0;
     for (int p = 0; p < N; ++p)
       for (int q = p + 1; q < N; ++q, ++k) {
@@ -723,8 +729,19 @@ __global__ void __launch_bounds__(256) adj_rev2(const AdjArgs a) {
         }
         phb[p] += a.four_over_eps * ph[q] * cb;
         phb[q] += a.four_over_eps * ph[p] * cb;
-        for (int d = 0; d < D; ++d)
-          a.A_H[(long long)(k * D + d) * V + y] = (inv != 0.0) ? (nvb[d] - nv[d] * nn) * inv : 0.0;
+        double Hb[D];
+        for (int d = 0; d < D; ++d) Hb[d] = (inv != 0.0) ? (nvb[d] - nv[d] * nn) * inv : 0.0;
+        if constexpr (MODEL == MODEL_BC) {
+          // H = phi_q G_p - phi_p G_q at this node: pointwise into G and phi
+          for (int d = 0; d < D; ++d) {
+            Gb[p][d] += ph[q] * Hb[d];
+            Gb[q][d] -= ph[p] * Hb[d];
+            phb[q] += G[p][d] * Hb[d];
+            phb[p] -= G[q][d] * Hb[d];
+          }
+        } else {
+          for (int d = 0; d < D; ++d) a.A_H[(long long)(k * D + d) * V + y] = Hb[d];
+        }
       }
   }
   for (int p = 0; p < N; ++p) {

@@ -659,8 +659,8 @@ AdjArgs adj_args(nphase_lbm_t h, void* ws) {
 hipError_t adj_launch(nphase_lbm_t h, int which, const AdjArgs& a) {
   const int grid = (int)((h->V + 255) / 256);
   if (h->lat == NPHASE_D2Q9)
-    return launch_adjoint<LAT_D2Q9>(h->N, h->prm.solve_all, h->prm.model, which, a, grid, h->stream);
-  return launch_adjoint<LAT_D3Q19>(h->N, h->prm.solve_all, h->prm.model, which, a, grid, h->stream);
+    return launch_adjoint<LAT_D2Q9>(h->N, h->prm.solve_all, step_model(h->prm), which, a, grid, h->stream);
+  return launch_adjoint<LAT_D3Q19>(h->N, h->prm.solve_all, step_model(h->prm), which, a, grid, h->stream);
 }
 
 int adj_check(nphase_lbm_t h) {
@@ -672,10 +672,6 @@ int adj_check(nphase_lbm_t h) {
   }
   if (h->prm.walls) {
     h->err = "the adjoint is built for periodic boundaries only";
-    return NPHASE_ENOTSUP;
-  }
-  if (step_model(h->prm) == MODEL_BC) {
-    h->err = "the adjoint is built for the stencil pair normals of Model B only";
     return NPHASE_ENOTSUP;
   }
   return NPHASE_OK;

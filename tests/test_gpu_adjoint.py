@@ -4,7 +4,7 @@
   pair-fraction guard is active) and random adjoint vectors, <lambda^t, ds> equals
   <lambda^{t+1}, (Step(s + h ds) - Step(s - h ds)) / 2h> with Step the oracle's step,
   for perturbations of each state component separately (f, g, u^{t-1}, phi^{t-1},
-  m_phi^{t-1}), D2Q9 and D3Q19, A and B;
+  m_phi^{t-1}), D2Q9 and D3Q19, A and B (both kinds of pair normals);
 * whole runs: dL/dsigma_pq and directional dL/dphi0 of a phase-field misfit against
   central finite differences of the oracle (<= 1e-4 relative);
 * checkpoint-every-k recomputation gives the same gradient as one segment (bitwise).
@@ -125,11 +125,16 @@ def _dot_test(cfg, phi, comp, h=1e-6, seed=0):
 @pytest.mark.parametrize("lattice,shape,model,solve_all", [
     ("D2Q9", (20, 24), "B", False), ("D2Q9", (20, 24), "A", False),
     ("D2Q9", (18, 22), "B", True), ("D3Q19", (8, 9, 10), "B", False),
-    ("D3Q19", (8, 9, 10), "A", False)])
+    ("D3Q19", (8, 9, 10), "A", False), ("D2Q9", (20, 24), "BC", False),
+    ("D3Q19", (8, 9, 10), "BC", True)])
 def test_adjoint_step_dot_product(lattice, shape, model, solve_all, comp):
-    cfg, phi = _mixture(lattice, shape, 3, seed=len(comp), model=model, solve_all=solve_all)
+    """BC: Model B with the chain-rule pair normals."""
+    cfg, phi = _mixture(lattice, shape, 3, seed=len(comp), model=model[0],
+                        solve_all=solve_all)
     if model == "A":
         cfg = dict(cfg, model_a_n=2)
+    if model == "BC":
+        cfg = dict(cfg, pair_normals="chain")
     fd, adj = _dot_test(cfg, phi, comp)
     print(f"  {lattice} {model} {comp}: fd={fd:.10e} adj={adj:.10e}")
     assert abs(adj - fd) <= 1e-6 * max(abs(fd), 1e-12)
