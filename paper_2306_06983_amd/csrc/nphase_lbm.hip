@@ -318,9 +318,10 @@ int nphase_lbm_create(const nphase_lbm_params* params, void* workspace_dev, size
   if (h->lat == NPHASE_D2Q9) {
     TX = TileShape<LAT_D2Q9>::TX; TY = TileShape<LAT_D2Q9>::TY; TZ = 1;
   } else {
-    // z-marching: columns x planes per workgroup
-    TX = h->prec == NPHASE_FP64 ? Z3Tile<double>::TX : Z3Tile<float>::TX;
-    TY = h->prec == NPHASE_FP64 ? Z3Tile<double>::TY : Z3Tile<float>::TY;
+    // z-marching: columns x planes per workgroup (the launch recomputes the counts for the
+    // column tile of its instantiation; these are those of the narrow tile)
+    TX = h->prec == NPHASE_FP64 ? Z3Tile<double, MAXN>::TX : Z3Tile<float, MAXN>::TX;
+    TY = h->prec == NPHASE_FP64 ? Z3Tile<double, MAXN>::TY : Z3Tile<float, MAXN>::TY;
     TZ = Z3_ZR;
   }
   h->ntx = (params->nx + TX - 1) / TX;

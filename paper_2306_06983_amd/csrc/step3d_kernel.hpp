@@ -42,13 +42,20 @@
 
 namespace nphase {
 
-// Column tile of a workgroup (TX * TY = 256 threads) and planes per run.  Rows of 64 (FP64)
+// Column tile of a workgroup (one thread per column) and planes per run.  Rows of 64 (FP64)
 // or 32 (FP32) nodes keep the x-shifted pushes of a wave on few partial cache lines; FP32
-// uses the narrower tile so that the Model B pair fractions still fit its LDS budget.
-template <typename T>
+// uses the narrower tile so that the Model B pair fractions still fit its LDS budget.  FP64
+// takes 64 x 8 columns (512 threads, one workgroup of 8 waves per CU, the waves of two
+// 64 x 4 ones) where the phi and tensor rings of NS evolved sets fit 160 KB: less x,y halo
+// recomputed per column (measured 2.5 % (Model B) to 6 % (Model A) on 256^3).
+template <typename T, int NS>
 struct Z3Tile {
   static constexpr int TX = sizeof(T) == 8 ? 64 : 32;
-  static constexpr int TY = 256 / TX;
+  static constexpr size_t LDS8 = sizeof(T) * (NS * 3 * (TX + 4) * 12 + 3 * 3 * (TX + 2) * 10);
+  static constexpr bool TALL = sizeof(T) == 8 && LDS8 <= 163840;
+  static constexpr int TY = TALL ? 8 : 256 / TX;
+  static constexpr int NT = TX * TY;
+  static constexpr int BUDGET = TALL ? 163840 : 81920;   // LDS of one workgroup
 };
 constexpr int Z3_ZR = 32;   // planes per workgroup run
 
@@ -230,22 +237,25 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) nphase_momen
 }
 
 template <typename T, int N, bool SA, int MODEL, int MODE>
-__global__ void __launch_bounds__(NTHREADS, 2) nphase_step3d_kernel(const StepArgs<T> a) {
+__global__ void __launch_bounds__((Z3Tile<T, (SA ? N : N - 1)>::NT), 2)
+    nphase_step3d_kernel(const StepArgs<T> a) {
   using L = Lattice<LAT_D3Q19>;
   constexpr int D = 3, Q = 19;
   constexpr int NS = SA ? N : N - 1;
   constexpr int NP = N * (N - 1) / 2;
   constexpr bool DEV = sizeof(T) == 4;
-  constexpr int TX = Z3Tile<T>::TX, TY = Z3Tile<T>::TY, ZR = Z3_ZR;
+  using ZT = Z3Tile<T, (SA ? N : N - 1)>;
+  constexpr int TX = ZT::TX, TY = ZT::TY, ZR = Z3_ZR;
   constexpr int RX = TX + 4, RY = TY + 4, RP = RX * RY;   // region plane (2-node ring)
   constexpr int IX = TX + 2, IY = TY + 2, IP = IX * IY;   // inner plane (1-node ring)
   constexpr int PHR = DEV ? 4 : 3;                        // phi ring depth
   constexpr int WR = 3;                                   // tensor ring depth
   constexpr T CS2 = T(1) / T(3);
-  // LDS budget: two workgroups (2 waves per SIMD) per CU in both precisions; the Model B
-  // pair fractions are staged when they fit, else recomputed at every stencil point
-  // (FP64: two waves per SIMD with the recomputation beat one wave with staged fractions)
-  constexpr int BUDGET = 81920;
+  // LDS budget: 2 waves per SIMD per CU in both precisions (two 256-thread workgroups or
+  // one 512-thread one); the Model B pair fractions are staged when they fit, else
+  // recomputed at every stencil point (FP64: two waves per SIMD with the recomputation beat
+  // one wave with staged fractions)
+  constexpr int BUDGET = ZT::BUDGET;
   constexpr int BASE = sizeof(T) * (NS * PHR * RP + 3 * WR * IP);
   constexpr bool PF_LDS = (MODEL == MODEL_B) && BASE + (int)sizeof(T) * NP * 3 * RP <= BUDGET;
 
@@ -355,8 +365,8 @@ __global__ void __launch_bounds__(NTHREADS, 2) nphase_step3d_kernel(const StepAr
   };
   auto s1_plane = [&](int z, auto wall) __attribute__((always_inline)) {
     s1_node(rown, col_own, z, wall);
-    constexpr int NRING = RP - NTHREADS;
-    for (int k = t; k < NRING; k += NTHREADS) {
+    constexpr int NRING = RP - ZT::NT;
+    for (int k = t; k < NRING; k += ZT::NT) {
       int rx, ry, rz;
       ring_coord<2, RX, RY, 1>(k, rx, ry, rz);
       s1_node(rx + RX * ry, col_of(rx, ry), z, wall);
@@ -518,9 +528,9 @@ __global__ void __launch_bounds__(NTHREADS, 2) nphase_step3d_kernel(const StepAr
     }
     // S2 (planes z0-1 .. zend)
     if (zs2 >= z0 - 1 && zs2 <= zend) {
-      constexpr int NIRING = IP - NTHREADS;
+      constexpr int NIRING = IP - ZT::NT;
       T G[N][D], Lp[N], R[N][D], phc[N], mphi[D];
-      for (int kk = t; kk < NIRING; kk += NTHREADS) {
+      for (int kk = t; kk < NIRING; kk += ZT::NT) {
         int ix, iy, iz;
         ring_coord<1, IX, IY, 1>(kk, ix, iy, iz);
         const int r = (ix + 1) + RX * (iy + 1);
