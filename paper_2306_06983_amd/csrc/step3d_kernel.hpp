@@ -44,16 +44,19 @@ namespace nphase {
 
 // Column tile of a workgroup (one thread per column) and planes per run.  Rows of 64 (FP64)
 // or 32 (FP32) nodes keep the x-shifted pushes of a wave on few partial cache lines; FP32
-// uses the narrower tile so that the Model B pair fractions still fit its LDS budget.  FP64
-// takes 64 x 8 columns (512 threads, one workgroup of 8 waves per CU, the waves of two
-// 64 x 4 ones) where the phi and tensor rings of NS evolved sets fit 160 KB: less x,y halo
-// recomputed per column (measured 2.5 % (Model B) to 6 % (Model A) on 256^3).
+// uses the narrower rows so that the Model B pair fractions still fit its LDS budget.  The
+// tile is twice as tall (512 threads, one workgroup of 8 waves per CU, the waves of two
+// 256-thread ones) where the phi and tensor rings of NS evolved sets then fit 160 KB: less
+// x,y halo recomputed per column (measured on 256^3: FP64 2.5 % (Model B) to 6 % (Model A),
+// FP32 1.3 % to 6 %).
 template <typename T, int NS>
 struct Z3Tile {
   static constexpr int TX = sizeof(T) == 8 ? 64 : 32;
-  static constexpr size_t LDS8 = sizeof(T) * (NS * 3 * (TX + 4) * 12 + 3 * 3 * (TX + 2) * 10);
-  static constexpr bool TALL = sizeof(T) == 8 && LDS8 <= 163840;
-  static constexpr int TY = TALL ? 8 : 256 / TX;
+  static constexpr int TY0 = 256 / TX, PHR_ = sizeof(T) == 4 ? 4 : 3;
+  static constexpr size_t LDS8 = sizeof(T) * (NS * PHR_ * (TX + 4) * (2 * TY0 + 4) +
+                                              3 * 3 * (TX + 2) * (2 * TY0 + 2));
+  static constexpr bool TALL = LDS8 <= 163840;
+  static constexpr int TY = TALL ? 2 * TY0 : TY0;
   static constexpr int NT = TX * TY;
   static constexpr int BUDGET = TALL ? 163840 : 81920;   // LDS of one workgroup
 };
