@@ -193,7 +193,7 @@ int nphase_lbm_load_state(nphase_lbm_t h, const void *state_dev);
 int nphase_lbm_state64_bytes(nphase_lbm_t h, size_t *bytes_host);
 int nphase_lbm_save_state64(nphase_lbm_t h, void *state64_dev);
 
-/* ---- Discrete adjoint (gravity = 0) -------------------------------------------------------
+/* ---- Discrete adjoint ------------------------------------------------------------------------
  * The hand-written reverse of one time step, in FP64 arithmetic.  With the state
  * s^{t+1} = Step(s^t; sigma) (the same step as nphase_lbm_step: Sec. 2.1 sources, Sec. 2.2
  * forces and mass flux, Sec. 3 collisions, recovery and streaming) and a scalar loss L, the
@@ -202,31 +202,36 @@ int nphase_lbm_save_state64(nphase_lbm_t h, void *state64_dev);
  * it is given are save_state64 buffers.  For FP32 handles this is the adjoint of the FP64
  * step evaluated along the FP32 trajectory.  Guarded points of the forward (normals below
  * the guard, pair fractions of absent pairs) are differentiated as the constants the
- * forward returns there.  The gravity reference density is treated as fixed, so these
- * entry points return NPHASE_ENOTSUP for non-zero gravity; they also return it for walls
- * (the reverse of the wall step is not built).  Both kinds of Model B pair normals are
- * differentiated.
+ * forward returns there.  The gravity force (rho - rho_bar) g depends on phi0 through the
+ * reference density rho_bar = mean density at t = 0: the steps accumulate dL/drho_bar beside
+ * the sigma partials and adjoint_init adds its share to dL/dphi0.  These entry points return
+ * NPHASE_ENOTSUP for walls (the reverse of the wall step is not built).  Both kinds of
+ * Model B pair normals are differentiated.
  *
  * adjoint_workspace_bytes: device scratch for one adjoint step (caller-owned).
  * adjoint_seed:  adj_state = dL/ds^T for L depending on the phase fields phi(T) [N][V]
  *                through dL_dphi_dev [N][nz][ny][nx] (phi_N = 1 - sum when N-1 sets are
  *                evolved).  Async.
  * adjoint_step:  adj_out = (dStep/ds^t)^T adj_in, given the forward state s^t (a
- *                save_state64 buffer); adds (dStep/dsigma_pq)^T adj_in to per-block partials in
- *                the workspace.  adj_in and adj_out must be different buffers.  Async.
+ *                save_state64 buffer); adds (dStep/dsigma_pq)^T adj_in and
+ *                (dStep/drho_bar)^T adj_in to per-block partials in the workspace.  adj_in and
+ *                adj_out must be different buffers.  Async.
  * adjoint_sigma: dL/dsigma_pq summed over the steps since the last reset, written to an
  *                N x N row-major host matrix with stride NPHASE_MAX_N (both [p][q] and [q][p]
  *                hold the derivative w.r.t. the pair tension; NULL skips); reset != 0 then
- *                clears the partials.  Synchronises when reading.
+ *                clears the partials (the rho_bar ones too).  Synchronises when reading.
  * adjoint_init:  dL/dphi0 [N][V] (device) from the adjoint of the initial state (f = w_i
- *                phi0, phi^{-1} = phi0); zero for the rebuilt last phase.  Async. */
+ *                phi0, phi^{-1} = phi0) plus the path through rho_bar accumulated in the
+ *                workspace since the last reset (so call it before the resetting
+ *                adjoint_sigma); zero for the rebuilt last phase.  Async. */
 int nphase_lbm_adjoint_workspace_bytes(nphase_lbm_t h, size_t *bytes_host);
 int nphase_lbm_adjoint_seed(nphase_lbm_t h, const double *dL_dphi_dev, void *adj_state_dev);
 int nphase_lbm_adjoint_step(nphase_lbm_t h, const void *fwd_state_dev, const void *adj_in_dev,
                             void *adj_out_dev, void *adj_ws_dev, size_t adj_ws_bytes);
 int nphase_lbm_adjoint_sigma(nphase_lbm_t h, void *adj_ws_dev, double *dL_dsigma_host,
                              int reset);
-int nphase_lbm_adjoint_init(nphase_lbm_t h, const void *adj_state_dev, double *dL_dphi0_dev);
+int nphase_lbm_adjoint_init(nphase_lbm_t h, const void *adj_state_dev, void *adj_ws_dev,
+                            size_t adj_ws_bytes, double *dL_dphi0_dev);
 
 /* Message of the last error on this handle (never NULL), and the name of a status code. */
 const char *nphase_lbm_last_error(nphase_lbm_t h);

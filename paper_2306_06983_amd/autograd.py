@@ -57,7 +57,7 @@ class NPhaseRun(torch.autograd.Function):
             for st in reversed(states):
                 sim.adjoint_step(st, lam, lam2, ws)
                 lam, lam2 = lam2, lam
-        dphi0 = sim.adjoint_init(lam)
+        dphi0 = sim.adjoint_init(lam, ws)
         dsig = sim.adjoint_sigma(ws, reset=True)
         N = ctx.N
         pairs = [dsig[p, q] for p in range(N) for q in range(p + 1, N)]

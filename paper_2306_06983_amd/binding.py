@@ -90,7 +90,7 @@ def load():
         "nphase_lbm_adjoint_seed": [vp, vp, vp],
         "nphase_lbm_adjoint_step": [vp, vp, vp, vp, vp, sz],
         "nphase_lbm_adjoint_sigma": [vp, vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int],
-        "nphase_lbm_adjoint_init": [vp, vp, vp],
+        "nphase_lbm_adjoint_init": [vp, vp, vp, sz, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -303,10 +303,14 @@ class Sim:
         m = np.array(out[:], dtype=np.float64).reshape(MAX_N, MAX_N)
         return m[:self.N, :self.N].copy()
 
-    def adjoint_init(self, lam):
+    def adjoint_init(self, lam, ws):
+        """dL/dphi0 from the adjoint of the initial state and the rho_bar partials in ws."""
         t = self.torch
+        buf, nbytes = ws
+        base = (buf.data_ptr() + 255) // 256 * 256
         out = t.empty((self.N,) + self.grid, dtype=t.float64, device=self.device)
         self._rc(self.lib.nphase_lbm_adjoint_init(self.h, ctypes.c_void_p(lam.data_ptr()),
+                                                  ctypes.c_void_p(base), nbytes,
                                                   ctypes.c_void_p(out.data_ptr())))
         return out
 

@@ -52,7 +52,9 @@ struct AdjArgs {
   double *F_phi, *F_j, *F_G, *F_L, *F_R, *F_H, *F_mphi, *F_W, *F_Fc;
   // adjoint intermediates
   double *A_ph, *A_j, *A_G, *A_R, *A_L, *A_mphi, *A_Fc, *A_gv, *A_um, *A_phm, *A_mmp, *A_H;
-  double* sig_partial;   // [pair][nblk], accumulated over the steps of a backward sweep
+  double* sig_partial;   // [pair + 1][nblk], accumulated over the steps of a backward sweep
+                         // (the last row: dL/drho_bar of the gravity force)
+  double* rb_total;      // dL/drho_bar summed over blocks (read by the init adjoint)
   // seed / init
   const double* dphi;    // dL/dphi [N][V]
   double* dphi0;         // dL/dphi0 [N][V]
@@ -260,11 +262,13 @@ __global__ void __launch_bounds__(256) adj_rev1(const AdjArgs a) {
   constexpr int Q = L::Q, D = L::D, NS = SA ? N : N - 1;
   constexpr double CS2 = 1.0 / 3.0;
   constexpr int NPAIR = N * (N - 1) / 2;
-  __shared__ double red[NPAIR > 0 ? NPAIR : 1][256];
+  // per-block partials: dL/dsigma_pq of every pair, then dL/drho_bar (gravity reference)
+  constexpr int NACC = NPAIR + 1;
+  __shared__ double red[NACC][256];
   const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long V = a.V;
-  double sig_loc[NPAIR > 0 ? NPAIR : 1];
-  for (int k = 0; k < NPAIR; ++k) sig_loc[k] = 0.0;
+  double sig_loc[NACC];
+  for (int k = 0; k < NACC; ++k) sig_loc[k] = 0.0;
   if (x < V) {
     Nbr<L> nb(x, a.nx, a.ny, a.nz);
     // ---------------- forward values at x
@@ -528,6 +532,7 @@ __global__ void __launch_bounds__(256) adj_rev1(const AdjArgs a) {
     for (int d = 0; d < D; ++d) {
       b_Fs[d] = b_F[d];
       b_rho += a.grav[d] * b_F[d];
+      sig_loc[NPAIR] -= a.grav[d] * b_F[d];   // the reference density rho_bar
       a.A_Fc[(long long)d * V + x] = b_F[d];
     }
     // grho = sum rho_p G_p ; Fs = sum mu_phi_p G_p
@@ -587,15 +592,15 @@ __global__ void __launch_bounds__(256) adj_rev1(const AdjArgs a) {
     for (int p = 0; p < NS; ++p) a.A_phm[(long long)p * V + x] = b_phm[p];
   }
   // deterministic per-block sigma partials
-  for (int k = 0; k < NPAIR; ++k) red[k][threadIdx.x] = sig_loc[k];
+  for (int k = 0; k < NACC; ++k) red[k][threadIdx.x] = sig_loc[k];
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s)
-      for (int k = 0; k < NPAIR; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+      for (int k = 0; k < NACC; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
     __syncthreads();
   }
   if (threadIdx.x == 0)
-    for (int k = 0; k < NPAIR; ++k) a.sig_partial[k * a.nblk + blockIdx.x] += red[k][0];
+    for (int k = 0; k < NACC; ++k) a.sig_partial[k * a.nblk + blockIdx.x] += red[k][0];
 }
 
 
@@ -846,9 +851,13 @@ __global__ void __launch_bounds__(256) adj_init(const AdjArgs a) {
   const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= a.V) return;
   const long long V = a.V;
+  // rho_bar = mean_x sum_q rho_q phi0_q (phi0_N = 1 - sum of the evolved ones): every
+  // node's phi0_p enters it with (rho_p [- rho_N]) / V
+  const double rbar_b = a.rb_total ? a.rb_total[0] : 0.0;
   for (int p = 0; p < NS; ++p) {
     double t = a.lpm_in[(long long)p * V + x];
     for (int i = 0; i < Q; ++i) t += L::w(i) * a.lf_in[(long long)(p * Q + i) * V + x];
+    t += rbar_b * (a.rho[p] - (SA ? 0.0 : a.rho[N - 1])) / (double)V;
     a.dphi0[(long long)p * V + x] = t;
   }
   if (!SA) a.dphi0[(long long)(N - 1) * V + x] = 0.0;   // the last phase is rebuilt

@@ -105,6 +105,22 @@ __global__ void __launch_bounds__(LOC_BLOCKS)
   }
 }
 
+// Fixed-order sum of n doubles into out[0] (one block of 256): the adjoint's dL/drho_bar
+// from its per-block partials.
+__global__ void __launch_bounds__(256)
+    sum_fixed_order_kernel(const double* __restrict__ v, int n, double* __restrict__ out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < n; b += 256) s += v[b];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
 // flag = 1 if any of the n values is not finite (flag cleared by the caller; every
 // writer stores the same value, so concurrent stores are benign).
 template <typename T>

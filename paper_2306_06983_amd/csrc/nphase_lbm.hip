@@ -581,7 +581,7 @@ namespace {
 
 struct AdjLayout {
   size_t F_phi, F_j, F_G, F_L, F_R, F_H, F_mphi, F_W, F_Fc;
-  size_t A_ph, A_j, A_G, A_R, A_L, A_mphi, A_Fc, A_gv, A_um, A_phm, A_mmp, A_H, sig;
+  size_t A_ph, A_j, A_G, A_R, A_L, A_mphi, A_Fc, A_gv, A_um, A_phm, A_mmp, A_H, sig, rb;
   size_t total;
   int nblk;
 };
@@ -600,8 +600,11 @@ AdjLayout adj_layout(nphase_lbm_t h) {
   L.A_ph = take(N); L.A_j = take(NS * D); L.A_G = take(N * D); L.A_R = take(N * D);
   L.A_L = take(N); L.A_mphi = take(D); L.A_Fc = take(D); L.A_gv = take(Q - 1); L.A_um = take(D);
   L.A_phm = take(NS); L.A_mmp = take(D); L.A_H = take(NP > 0 ? NP * D : 1);
+  // per-block partials of every pair's dL/dsigma and of dL/drho_bar, then their sum
   L.sig = off;
-  off += align_up((size_t)(NP > 0 ? NP : 1) * L.nblk * b);
+  off += align_up((size_t)(NP + 1) * L.nblk * b);
+  L.rb = off;
+  off += align_up(b);
   L.total = off;
   return L;
 }
@@ -635,6 +638,7 @@ AdjArgs adj_args(nphase_lbm_t h, void* ws) {
   a.A_Fc = (double*)(w + L.A_Fc); a.A_gv = (double*)(w + L.A_gv); a.A_um = (double*)(w + L.A_um);
   a.A_phm = (double*)(w + L.A_phm); a.A_mmp = (double*)(w + L.A_mmp); a.A_H = (double*)(w + L.A_H);
   a.sig_partial = (double*)(w + L.sig);
+  a.rb_total = (double*)(w + L.rb);
   a.nblk = L.nblk;
   const nphase_lbm_params& p = h->prm;
   a.nx = p.nx; a.ny = p.ny; a.nz = p.nz; a.V = h->V; a.model_a_n = p.model_a_n;
@@ -667,10 +671,6 @@ hipError_t adj_launch(nphase_lbm_t h, int which, const AdjArgs& a) {
 int adj_check(nphase_lbm_t h) {
   int rc = check_handle(h);
   if (rc) return rc;
-  if (h->prm.gravity[0] != 0.0 || h->prm.gravity[1] != 0.0 || h->prm.gravity[2] != 0.0) {
-    h->err = "the adjoint treats the gravity reference density as fixed: needs gravity = 0";
-    return NPHASE_ENOTSUP;
-  }
   if (h->prm.walls) {
     h->err = "the adjoint is built for periodic boundaries only";
     return NPHASE_ENOTSUP;
@@ -748,7 +748,7 @@ int nphase_lbm_adjoint_sigma(nphase_lbm_t h, void* adj_ws_dev, double* dL_dsigma
       }
   }
   if (reset) {
-    const long long n = (long long)(NP > 0 ? NP : 1) * L.nblk;
+    const long long n = (long long)(NP + 1) * L.nblk;
     hipLaunchKernelGGL(zero_double_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->stream, part, n);
     HIPCHK(hipGetLastError(), "sigma reset");
   }
@@ -798,16 +798,21 @@ int nphase_lbm_save_state64(nphase_lbm_t h, void* state_dev) {
   return NPHASE_OK;
 }
 
-int nphase_lbm_adjoint_init(nphase_lbm_t h, const void* adj_state_dev, double* dL_dphi0_dev) {
+int nphase_lbm_adjoint_init(nphase_lbm_t h, const void* adj_state_dev, void* adj_ws_dev,
+                            size_t adj_ws_bytes, double* dL_dphi0_dev) {
   int rc = adj_check(h);
   if (rc) return rc;
-  if (!adj_state_dev || !dL_dphi0_dev) { h->err = "NULL pointer"; return NPHASE_EINVAL; }
-  AdjArgs a;
-  std::memset(&a, 0, sizeof(a));
-  a.V = h->V; a.nx = h->prm.nx; a.ny = h->prm.ny; a.nz = h->prm.nz;
+  if (!adj_state_dev || !dL_dphi0_dev || !adj_ws_dev) { h->err = "NULL pointer"; return NPHASE_EINVAL; }
+  if (adj_ws_bytes < adj_layout(h).total) { h->err = "adjoint workspace too small"; return NPHASE_ENOMEM; }
+  AdjArgs a = adj_args(h, adj_ws_dev);
   const StatePtrs li = state_ptrs(h, adj_state_dev);
   a.lf_in = li.f; a.lpm_in = li.pm;
   a.dphi0 = dL_dphi0_dev;
+  // dL/drho_bar accumulated by the adjoint steps since the last reset of the partials
+  const int NP = h->N * (h->N - 1) / 2;
+  hipLaunchKernelGGL(sum_fixed_order_kernel, dim3(1), dim3(256), 0, h->stream,
+                     (const double*)(a.sig_partial + (size_t)NP * a.nblk), a.nblk, a.rb_total);
+  HIPCHK(hipGetLastError(), "rho_bar adjoint");
   HIPCHK(adj_launch(h, ADJ_INIT, a), "adjoint init");
   return NPHASE_OK;
 }

@@ -6,7 +6,8 @@
   for perturbations of each state component separately (f, g, u^{t-1}, phi^{t-1},
   m_phi^{t-1}), D2Q9 and D3Q19, A and B (both kinds of pair normals);
 * whole runs: dL/dsigma_pq and directional dL/dphi0 of a phase-field misfit against
-  central finite differences of the oracle (<= 1e-4 relative);
+  central finite differences of the oracle (<= 1e-4 relative), with and without gravity
+  (whose reference density depends on phi0);
 * checkpoint-every-k recomputation gives the same gradient as one segment (bitwise).
 """
 import numpy as np
@@ -140,8 +141,9 @@ def test_adjoint_step_dot_product(lattice, shape, model, solve_all, comp):
     assert abs(adj - fd) <= 1e-6 * max(abs(fd), 1e-12)
 
 
-def _loss_setup(model="B", n=48, steps=60):
+def _loss_setup(model="B", n=48, steps=60, gravity=(0.0, 0.0, 0.0)):
     cfg, phi = inputs.many_discs(n=n, N=3, count=3, rmin=6, rmax=9, model=model, seed=12)
+    cfg = dict(cfg, gravity=list(gravity))
     rng = np.random.default_rng(5)
     target_pairs = inputs.sigma_pairs(cfg) * rng.uniform(0.8, 1.2, size=3)
     cfg_t = inputs.with_sigma_pairs(cfg, target_pairs)
@@ -158,12 +160,15 @@ def _oracle_loss(cfg, phi, target, steps):
     return 0.5 * float(((ph - target) ** 2).sum())
 
 
-@pytest.mark.parametrize("model", ["B", "A"])
-def test_adjoint_gradient_vs_oracle_fd(model):
+@pytest.mark.parametrize("model,gravity", [("B", (0.0, 0.0, 0.0)), ("A", (0.0, 0.0, 0.0)),
+                                           ("B", (0.0, -2e-5, 0.0))])
+def test_adjoint_gradient_vs_oracle_fd(model, gravity):
+    """With gravity the force (rho - rho_bar) g also depends on phi0 through rho_bar (the
+    directions below change the mean density: the densities differ)."""
     import torch
     from paper_2306_06983_amd.autograd import run_differentiable
     steps = 60
-    cfg, phi, target = _loss_setup(model, steps=steps)
+    cfg, phi, target = _loss_setup(model, steps=steps, gravity=gravity)
     pairs = inputs.sigma_pairs(cfg)
     phi0 = torch.tensor(phi, dtype=torch.float64, device="cuda:0", requires_grad=True)
     sp = torch.tensor(pairs, dtype=torch.float64, requires_grad=True)
