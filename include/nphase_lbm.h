@@ -204,9 +204,10 @@ int nphase_lbm_save_state64(nphase_lbm_t h, void *state64_dev);
  * the guard, pair fractions of absent pairs) are differentiated as the constants the
  * forward returns there.  The gravity force (rho - rho_bar) g depends on phi0 through the
  * reference density rho_bar = mean density at t = 0: the steps accumulate dL/drho_bar beside
- * the sigma partials and adjoint_init adds its share to dL/dphi0.  These entry points return
- * NPHASE_ENOTSUP for walls (the reverse of the wall step is not built).  Both kinds of
- * Model B pair normals are differentiated.
+ * the sigma partials and adjoint_init adds its share to dL/dphi0.  With walls the reverse
+ * covers the half-way bounce-back of both distributions, the wetting ghosts of phi (and of
+ * the Model B pair fractions formed from them) and the odd reflection of the F_c tensor.
+ * Both kinds of Model B pair normals are differentiated.
  *
  * adjoint_workspace_bytes: device scratch for one adjoint step (caller-owned).
  * adjoint_seed:  adj_state = dL/ds^T for L depending on the phase fields phi(T) [N][V]

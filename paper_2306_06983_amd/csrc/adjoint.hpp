@@ -66,26 +66,54 @@ struct AdjArgs {
   double dbeta2[MAXN * MAXN];   // d(2 beta_pq)/d sigma_pq = 6 / eps
   double dkappa[MAXN * MAXN];   // d(k_pq)/d sigma_pq = -3 eps / 4
   double mob, s1, four_over_eps, rho_bar, grav[3];
+  // walls at both ends of the slowest axis (y in 2D, z in 3D) and, per unordered pair
+  // p < q, (4 / eps) cos theta_pq of the wetting condition
+  int walls;
+  double wet[MAXN * (MAXN - 1) / 2];
 };
 
+// Neighbours of node x.  The axes are periodic except, with walls, the slowest one: there a
+// node x + s c_i beyond the first or the last plane lies behind a wall (cross), and the
+// stencils read a ghost built from the fluid node facing it, x + s c_i with its
+// wall-normal component dropped (facing).
 template <class L>
 struct Nbr {
   int X[3], Y[3], Z[3];
   int nx, ny;
-  __device__ Nbr(long long x, int nx_, int ny_, int nz_) : nx(nx_), ny(ny_) {
+  bool lo, hi;   // x on the first / last plane of the wall-bounded axis, with walls
+  __device__ Nbr(long long x, int nx_, int ny_, int nz_, int walls = 0) : nx(nx_), ny(ny_) {
     const int ix = (int)(x % nx_);
     const int iy = (int)((x / nx_) % ny_);
     const int iz = (int)(x / ((long long)nx_ * ny_));
     X[0] = wrap(ix - 1, nx_); X[1] = ix; X[2] = wrap(ix + 1, nx_);
     Y[0] = wrap(iy - 1, ny_); Y[1] = iy; Y[2] = wrap(iy + 1, ny_);
     Z[0] = wrap(iz - 1, nz_); Z[1] = iz; Z[2] = wrap(iz + 1, nz_);
+    const int k = (L::D == 2) ? iy : iz, nw = (L::D == 2) ? ny_ : nz_;
+    lo = walls && k == 0;
+    hi = walls && k == nw - 1;
   }
-  // node x + s * c_i (s = +1 or -1)
+  // node x + s * c_i (s = +1 or -1), periodic in every axis
   __device__ long long at(int i, int s) const {
     return (long long)X[s * L::c(i, 0) + 1] +
            (long long)nx * ((long long)Y[s * L::c(i, 1) + 1] + (long long)ny * Z[s * L::c(i, 2) + 1]);
   }
+  // x + s * c_i lies behind a wall
+  __device__ bool cross(int i, int s) const {
+    const int cw = s * L::c(i, L::D - 1);
+    return (cw < 0 && lo) || (cw > 0 && hi);
+  }
+  // x + s * c_i without its wall-normal component: the fluid node a ghost stands for
+  __device__ long long facing(int i, int s) const {
+    const int cy = (L::D == 3) ? s * L::c(i, 1) : 0;
+    return (long long)X[s * L::c(i, 0) + 1] + (long long)nx * ((long long)Y[cy + 1] + (long long)ny * Z[1]);
+  }
 };
+
+// all N order parameters at node y (the last one rebuilt where N - 1 sets are evolved)
+template <int N>
+__device__ __forceinline__ void phases_at(const AdjArgs& a, long long y, double* ph) {
+  for (int p = 0; p < N; ++p) ph[p] = a.F_phi[(long long)p * a.V + y];
+}
 
 __device__ __forceinline__ double gsecond(double p) {   // d/dphi g'(phi) = 2 - 12 phi + 12 phi^2
   return 2.0 - 12.0 * p + 12.0 * p * p;
@@ -128,7 +156,7 @@ __global__ void __launch_bounds__(256) adj_fwd2(const AdjArgs a) {
   const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= a.V) return;
   const long long V = a.V;
-  Nbr<L> nb(x, a.nx, a.ny, a.nz);
+  Nbr<L> nb(x, a.nx, a.ny, a.nz, a.walls);
   double phc[N], G[N][D], Lp[N], R[N][D], H[NP > 0 ? NP : 1][D];
   for (int p = 0; p < N; ++p) {
     phc[p] = a.F_phi[(long long)p * V + x];
@@ -139,10 +167,16 @@ __global__ void __launch_bounds__(256) adj_fwd2(const AdjArgs a) {
     for (int d = 0; d < D; ++d) H[k][d] = 0.0;
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
-    const long long y = nb.at(i, 1);
     const double wg = 3.0 * L::w(i), wl = 6.0 * L::w(i);
     double ph[N];
-    for (int p = 0; p < N; ++p) ph[p] = a.F_phi[(long long)p * V + y];
+    if (nb.cross(i, 1)) {
+      // ghost behind the wall: the wetting condition of the facing fluid node
+      double pf[N];
+      phases_at<N>(a, nb.facing(i, 1), pf);
+      wetting_ghost<double, N>(a, pf, ph);
+    } else {
+      phases_at<N>(a, nb.at(i, 1), ph);
+    }
     for (int p = 0; p < N; ++p) {
       for (int d = 0; d < D; ++d) G[p][d] += wg * (double)L::c(i, d) * ph[p];
       Lp[p] += wl * (ph[p] - phc[p]);
@@ -230,13 +264,15 @@ __global__ void __launch_bounds__(256) adj_fwd3(const AdjArgs a) {
   const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= a.V) return;
   const long long V = a.V;
-  Nbr<L> nb(x, a.nx, a.ny, a.nz);
+  Nbr<L> nb(x, a.nx, a.ny, a.nz, a.walls);
   double DW[NW][D];
   for (int k = 0; k < NW; ++k) for (int d = 0; d < D; ++d) DW[k][d] = 0.0;
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
-    const long long y = nb.at(i, 1);
-    const double wg = 3.0 * L::w(i);
+    // behind a wall the tensor is the odd reflection of the facing node's
+    const bool cr = nb.cross(i, 1);
+    const long long y = cr ? nb.facing(i, 1) : nb.at(i, 1);
+    const double wg = cr ? -3.0 * L::w(i) : 3.0 * L::w(i);
     for (int k = 0; k < NW; ++k) {
       const double v = a.F_W[(long long)k * V + y];
       for (int d = 0; d < D; ++d) DW[k][d] += wg * (double)L::c(i, d) * v;
@@ -270,7 +306,17 @@ __global__ void __launch_bounds__(256) adj_rev1(const AdjArgs a) {
   double sig_loc[NACC];
   for (int k = 0; k < NACC; ++k) sig_loc[k] = 0.0;
   if (x < V) {
-    Nbr<L> nb(x, a.nx, a.ny, a.nz);
+    Nbr<L> nb(x, a.nx, a.ny, a.nz, a.walls);
+    // the push of x in direction i lands at x + c_i, or behind a wall (half-way
+    // bounce-back) in the opposite slot of x itself
+    auto dest = [&](int i, long long& node) -> int {
+      if (nb.cross(i, 1)) {
+        node = x;
+        return opposite<L>(i);
+      }
+      node = nb.at(i, 1);
+      return i;
+    };
     // ---------------- forward values at x
     double ph[N], j[NS][D], G[N][D], Lp[N], R[N][D], mphi[D], Fc[D], gv[Q], um[D], phm[N], mmp[D];
     for (int p = 0; p < N; ++p) {
@@ -384,7 +430,9 @@ __global__ void __launch_bounds__(256) adj_rev1(const AdjArgs a) {
     for (int p = 0; p < NS; ++p) b_ph[p] = a.lpm_in[(long long)p * V + x];   // phi^t -> phi^{t-1}
     // flow collision, i >= 1 (pull: g*_i(x) went to x + c_i)
     for (int i = 1; i < Q; ++i) {
-      const double lg = a.lg_in[(long long)(i - 1) * V + nb.at(i, 1)];
+      long long xd;
+      const int id = dest(i, xd);
+      const double lg = a.lg_in[(long long)(id - 1) * V + xd];
       const double wi = L::w(i);
       double cu = 0.0, cm = 0.0;
       for (int d = 0; d < D; ++d) {
@@ -461,7 +509,9 @@ __global__ void __launch_bounds__(256) adj_rev1(const AdjArgs a) {
       double b_A[D], b_D[D];
       for (int d = 0; d < D; ++d) b_A[d] = b_D[d] = 0.0;
       for (int i = 0; i < Q; ++i) {
-        const double t = a.lf_in[(long long)(p * Q + i) * V + nb.at(i, 1)];
+        long long xd;
+        const int id = dest(i, xd);
+        const double t = a.lf_in[(long long)(p * Q + id) * V + xd];
         const double wi = L::w(i);
         b_ph[p] += wi * t;
         for (int d = 0; d < D; ++d) {
@@ -614,14 +664,13 @@ __global__ void __launch_bounds__(256) adj_rev2(const AdjArgs a) {
   const long long y = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (y >= a.V) return;
   const long long V = a.V;
-  Nbr<L> nb(y, a.nx, a.ny, a.nz);
-  // W(y) enters F_c(y - c_i) for every i
+  Nbr<L> nb(y, a.nx, a.ny, a.nz, a.walls);
+  // W(y) enters F_c(y - c_i) for every i whose y - c_i is fluid, and with walls, negated,
+  // F_c of the node y - c_i in-plane when y + c_i lies behind a wall (that node reads the
+  // ghost facing y in direction i)
   double Wb[NW];
   for (int k = 0; k < NW; ++k) Wb[k] = 0.0;
-#pragma unroll
-  for (int i = 1; i < Q; ++i) {
-    const long long x = nb.at(i, -1);
-    const double wg = 3.0 * L::w(i);
+  auto take = [&](int i, long long x, double wg) {
     double Fb[D];
     for (int d = 0; d < D; ++d) Fb[d] = a.A_Fc[(long long)d * V + x];
     const double cx = L::c(i, 0), cy = L::c(i, 1), cz = L::c(i, 2);
@@ -630,6 +679,11 @@ __global__ void __launch_bounds__(256) adj_rev2(const AdjArgs a) {
       Wb[1] += wg * (0.5 * cz * Fb[0] - 0.5 * cx * Fb[2]);
       Wb[2] += wg * (0.5 * cz * Fb[1] - 0.5 * cy * Fb[2]);
     }
+  };
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    if (!nb.cross(i, -1)) take(i, nb.at(i, -1), 3.0 * L::w(i));
+    if (nb.cross(i, 1)) take(i, nb.facing(i, -1), -3.0 * L::w(i));
   }
   double m[D], u[D], mb[D], ub[D];
   for (int d = 0; d < D; ++d) {
@@ -764,7 +818,7 @@ __global__ void __launch_bounds__(256) adj_rev3(const AdjArgs a) {
   const long long z = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (z >= a.V) return;
   const long long V = a.V;
-  Nbr<L> nb(z, a.nx, a.ny, a.nz);
+  Nbr<L> nb(z, a.nx, a.ny, a.nz, a.walls);
   double phb[N], ph[N];
   double lsum = 0.0;
   for (int i = 1; i < Q; ++i) lsum += 6.0 * L::w(i);
@@ -774,20 +828,60 @@ __global__ void __launch_bounds__(256) adj_rev3(const AdjArgs a) {
   }
   double pfb[NP > 0 ? NP : 1];
   for (int k = 0; k < NP; ++k) pfb[k] = 0.0;
-#pragma unroll
-  for (int i = 1; i < Q; ++i) {
-    const long long x = nb.at(i, -1);   // phi(z) entered the stencils at z - c_i
+  // phi(z) entered the stencils of z - c_i (direction i) where that node is fluid; with
+  // walls the ghost facing z entered those of the node z - c_i in-plane (direction i) when
+  // z + c_i lies behind a wall: its adjoint (ghb, and gpfb for the ghost pair fractions)
+  // goes back through the wetting condition below
+  double ghb[N], gpfb[NP > 0 ? NP : 1];
+  for (int p = 0; p < N; ++p) ghb[p] = 0.0;
+  for (int k = 0; k < NP; ++k) gpfb[k] = 0.0;
+  auto take = [&](int i, long long x, double* b, double* bpf) {
     const double wg = 3.0 * L::w(i), wl = 6.0 * L::w(i);
     for (int p = 0; p < N; ++p) {
       double t = wl * a.A_L[(long long)p * V + x];
       for (int d = 0; d < D; ++d)
         if (L::c(i, d) != 0) t += wg * (double)L::c(i, d) * a.A_G[(long long)(p * D + d) * V + x];
-      phb[p] += t;
+      b[p] += t;
     }
     if constexpr (MODEL == MODEL_B) {
       for (int k = 0; k < NP; ++k)
         for (int d = 0; d < D; ++d)
-          if (L::c(i, d) != 0) pfb[k] += wg * (double)L::c(i, d) * a.A_H[(long long)(k * D + d) * V + x];
+          if (L::c(i, d) != 0) bpf[k] += wg * (double)L::c(i, d) * a.A_H[(long long)(k * D + d) * V + x];
+    }
+  };
+  bool ghost = false;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    if (!nb.cross(i, -1)) take(i, nb.at(i, -1), phb, pfb);
+    if (nb.cross(i, 1)) {
+      take(i, nb.facing(i, -1), ghb, gpfb);
+      ghost = true;
+    }
+  }
+  if (ghost) {
+    // ghost phi_p = phi_p + sum_{q != p} (4/eps) cos theta_pq phi_p phi_q at z
+    double gh[N];
+    wetting_ghost<double, N>(a, ph, gh);
+    if constexpr (MODEL == MODEL_B) {
+      int k = 0;
+      for (int p = 0; p < N; ++p)
+        for (int q = p + 1; q < N; ++q, ++k) {
+          const double s = gh[p] + gh[q];
+          if (s > PAIR_EPS) {
+            const double inv2 = 1.0 / (s * s);
+            ghb[p] += gh[q] * inv2 * gpfb[k];
+            ghb[q] -= gh[p] * inv2 * gpfb[k];
+          }
+        }
+    }
+    int k = 0;
+    for (int p = 0; p < N; ++p) {
+      phb[p] += ghb[p];
+      for (int q = p + 1; q < N; ++q, ++k) {
+        const double vb = a.wet[k] * (ghb[p] - ghb[q]);
+        phb[p] += ph[q] * vb;
+        phb[q] += ph[p] * vb;
+      }
     }
   }
   if constexpr (MODEL == MODEL_B) {

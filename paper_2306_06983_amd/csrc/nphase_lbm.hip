@@ -153,6 +153,27 @@ int fail_hip(nphase_lbm_t h, hipError_t e, const char* where) {
     if (e_ != hipSuccess) return fail_hip(h, e_, where); \
   } while (0)
 
+// Wetting coefficients (4/eps) cos theta_pq per unordered pair p < q (lexicographic): the
+// N - 1 angles theta_pN are given, the others follow from Young's relation (Sec. 4.2),
+// cos theta_pq = (sigma_pN cos theta_pN - sigma_qN cos theta_qN) / sigma_pq; cos theta_qp =
+// -cos theta_pq.  Zero without walls.
+void wetting_coefficients(const nphase_lbm_params& p, int N, double* wet) {
+  const int last = N - 1;
+  for (int i = 0, k = 0; i < N; ++i) {
+    for (int j = i + 1; j < N; ++j, ++k) {
+      double c;
+      if (j == last) {
+        c = p.contact_cos[i];
+      } else {
+        const double s_iN = p.sigma[i * NPHASE_MAX_N + last];
+        const double s_jN = p.sigma[j * NPHASE_MAX_N + last];
+        c = (s_iN * p.contact_cos[i] - s_jN * p.contact_cos[j]) / p.sigma[i * NPHASE_MAX_N + j];
+      }
+      wet[k] = p.walls ? 4.0 / p.eps * c : 0.0;
+    }
+  }
+}
+
 template <typename T>
 void fill_args(nphase_lbm_t h, StepArgs<T>* out) {
   const nphase_lbm_params& p = h->prm;
@@ -195,22 +216,9 @@ void fill_args(nphase_lbm_t h, StepArgs<T>* out) {
     a.rho_bar = (T)h->rho_bar;
     for (int d = 0; d < 3; ++d) a.grav[d] = (T)p.gravity[d];
     a.walls = p.walls;
-    // wetting: (4/eps) cos theta_pq per pair p < q; cos theta_pN given, the other pairs
-    // from Young's relation (Sec. 4.2); cos theta_qp = -cos theta_pq
-    const int last = h->N - 1;
-    for (int i = 0, k = 0; i < h->N; ++i) {
-      for (int j = i + 1; j < h->N; ++j, ++k) {
-        double c;
-        if (j == last) {
-          c = p.contact_cos[i];
-        } else {
-          const double s_iN = p.sigma[i * NPHASE_MAX_N + last];
-          const double s_jN = p.sigma[j * NPHASE_MAX_N + last];
-          c = (s_iN * p.contact_cos[i] - s_jN * p.contact_cos[j]) / p.sigma[i * NPHASE_MAX_N + j];
-        }
-        a.wet[k] = p.walls ? (T)(4.0 / p.eps * c) : T(0);
-      }
-    }
+    double wet[MAXN * (MAXN - 1) / 2];
+    wetting_coefficients(p, h->N, wet);
+    for (int k = 0; k < h->N * (h->N - 1) / 2; ++k) a.wet[k] = (T)wet[k];
   }
 }
 
@@ -658,6 +666,8 @@ AdjArgs adj_args(nphase_lbm_t h, void* ws) {
   a.four_over_eps = 4.0 / p.eps;
   a.rho_bar = h->rho_bar;
   for (int d = 0; d < 3; ++d) a.grav[d] = p.gravity[d];
+  a.walls = p.walls;
+  wetting_coefficients(p, h->N, a.wet);
   return a;
 }
 
@@ -669,13 +679,7 @@ hipError_t adj_launch(nphase_lbm_t h, int which, const AdjArgs& a) {
 }
 
 int adj_check(nphase_lbm_t h) {
-  int rc = check_handle(h);
-  if (rc) return rc;
-  if (h->prm.walls) {
-    h->err = "the adjoint is built for periodic boundaries only";
-    return NPHASE_ENOTSUP;
-  }
-  return NPHASE_OK;
+  return check_handle(h);
 }
 
 }  // namespace

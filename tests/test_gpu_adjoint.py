@@ -5,9 +5,11 @@
   <lambda^{t+1}, (Step(s + h ds) - Step(s - h ds)) / 2h> with Step the oracle's step,
   for perturbations of each state component separately (f, g, u^{t-1}, phi^{t-1},
   m_phi^{t-1}), D2Q9 and D3Q19, A and B (both kinds of pair normals);
+* the same with walls (half-way bounce-back, wetting ghosts, the odd F_c tensor) at both
+  ends of the slowest axis, down to two rows between the walls;
 * whole runs: dL/dsigma_pq and directional dL/dphi0 of a phase-field misfit against
   central finite differences of the oracle (<= 1e-4 relative), with and without gravity
-  (whose reference density depends on phi0);
+  (whose reference density depends on phi0), and with walls (drops wetting both walls);
 * checkpoint-every-k recomputation gives the same gradient as one segment (bitwise).
 """
 import numpy as np
@@ -74,9 +76,15 @@ def _oracle_to_vector(st):
     return np.concatenate(parts)
 
 
-def _dot_test(cfg, phi, comp, h=1e-6, seed=0):
+def _dot_test(cfg, phi, comp, h=None, seed=0):
     """<adjoint_step(s)^T lam, ds> against <lam, central difference of the oracle's step
-    along ds> at a state s taken from the GPU run (in the FP64 population layout)."""
+    along ds> at a state s taken from the GPU run (in the FP64 population layout).
+    One step is affine in phi^{t-1} and in m_phi^{t-1} (they enter the Euler derivative of
+    m.u in the pressure, the tensor T and Z = 3 d_t(phi u) + R linearly), so the central
+    difference along those is exact for any step and a large one (1e-3) keeps its round-off
+    low; the other components take 1e-6."""
+    if h is None:
+        h = 1e-3 if comp in ("pm", "mm") else 1e-6
     import torch
     from paper_2306_06983_amd import binding as B
     sim = B.Sim(cfg, "fp64").init(phi)
@@ -138,6 +146,27 @@ def test_adjoint_step_dot_product(lattice, shape, model, solve_all, comp):
         cfg = dict(cfg, pair_normals="chain")
     fd, adj = _dot_test(cfg, phi, comp)
     print(f"  {lattice} {model} {comp}: fd={fd:.10e} adj={adj:.10e}")
+    assert abs(adj - fd) <= 1e-6 * max(abs(fd), 1e-12)
+
+
+@pytest.mark.parametrize("comp", ["f", "g", "u", "pm", "mm"])
+@pytest.mark.parametrize("lattice,shape,model,solve_all", [
+    ("D2Q9", (21, 20), "B", False), ("D2Q9", (21, 20), "A", False),
+    ("D2Q9", (2, 16), "B", True), ("D2Q9", (13, 18), "BC", False),
+    ("D3Q19", (9, 8, 10), "B", False), ("D3Q19", (7, 8, 9), "A", True),
+    ("D3Q19", (2, 8, 8), "BC", False)])
+def test_adjoint_step_dot_product_walls(lattice, shape, model, solve_all, comp):
+    """Walls before the first and after the last plane of the slowest axis (shape[0]), with
+    contact angles away from 90 degrees so that the ghosts differ from the facing nodes."""
+    cfg, phi = _mixture(lattice, shape, 3, seed=3 + len(comp), model=model[0],
+                        solve_all=solve_all)
+    cfg = dict(cfg, walls=True, contact_cos=[0.45, -0.3])
+    if model == "A":
+        cfg = dict(cfg, model_a_n=2)
+    if model == "BC":
+        cfg = dict(cfg, pair_normals="chain")
+    fd, adj = _dot_test(cfg, phi, comp)
+    print(f"  walls {lattice} {shape} {model} {comp}: fd={fd:.10e} adj={adj:.10e}")
     assert abs(adj - fd) <= 1e-6 * max(abs(fd), 1e-12)
 
 
@@ -211,6 +240,77 @@ def test_adjoint_gradient_vs_oracle_fd(model, gravity):
               _oracle_loss(cfg, phi - h * dirn, target, steps)) / (2 * h)
         adj = float((gphi * dirn).sum())
         print(f"  dL/dphi0 . d{r}: adjoint {adj:.8e} fd {fd:.8e}")
+        assert abs(adj - fd) <= 1e-4 * abs(fd)
+
+
+def _walled_loss_setup(model, steps, gravity):
+    """48 x 32 box, walls below row 0 and above row 31: a drop of phase 0 on the bottom
+    wall, one of phase 1 on the top wall, phase 2 around them; target = the run with the
+    pair tensions scaled by seeded U[0.8, 1.2]."""
+    nx, ny = 48, 32
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    r0 = np.hypot(x - 16.5, y + 0.5)
+    r1 = np.hypot(x - 31.5, y - ny + 0.5)
+    p0 = 0.5 + 0.5 * np.tanh(2.0 * (9.0 - r0) / 4.0)
+    p1 = 0.5 + 0.5 * np.tanh(2.0 * (8.0 - r1) / 4.0)
+    phi = np.stack([p0, p1, 1.0 - p0 - p1])
+    rng = np.random.default_rng(17)
+    sig = inputs.random_sigma(3, rng, 0.005, 0.02)
+    cfg = inputs.base_cfg("D2Q9", nx, ny, 1, 3, sig, [2.0, 1.5, 1.0], [0.8, 0.7, 0.9],
+                          mobility=0.05, eps=4.0, model=model, gravity=gravity)
+    cfg = dict(cfg, walls=True, contact_cos=[0.5, -0.35])
+    target_pairs = inputs.sigma_pairs(cfg) * rng.uniform(0.8, 1.2, size=3)
+    Ct = O.Config(inputs.with_sigma_pairs(cfg, target_pairs))
+    target = O.fields(Ct, O.step(Ct, O.init(Ct, phi), steps))[0]
+    return cfg, phi, target
+
+
+@pytest.mark.parametrize("model,gravity", [("B", (0.0, -1e-5, 0.0)), ("A", (0.0, 0.0, 0.0))])
+def test_adjoint_gradient_walls_vs_oracle_fd(model, gravity):
+    import torch
+    from paper_2306_06983_amd.autograd import run_differentiable
+    steps = 60
+    cfg, phi, target = _walled_loss_setup(model, steps, gravity)
+    pairs = inputs.sigma_pairs(cfg)
+    phi0 = torch.tensor(phi, dtype=torch.float64, device="cuda:0", requires_grad=True)
+    sp = torch.tensor(pairs, dtype=torch.float64, requires_grad=True)
+    phiT = run_differentiable(cfg, phi0, sp, steps, ckpt_every=25)
+    loss = 0.5 * ((phiT - torch.tensor(target, device="cuda:0")) ** 2).sum()
+    loss.backward()
+    gs = sp.grad.numpy()
+    gphi = phi0.grad.detach().cpu().numpy()
+    fds = []
+    for k in range(3):
+        fk = []
+        for rel in (1e-4, 5e-5):
+            h = rel * pairs[k]
+            pp, pm = pairs.copy(), pairs.copy()
+            pp[k] += h
+            pm[k] -= h
+            fk.append((_oracle_loss(inputs.with_sigma_pairs(cfg, pp), phi, target, steps) -
+                       _oracle_loss(inputs.with_sigma_pairs(cfg, pm), phi, target, steps)) /
+                      (2 * h))
+        fds.append(fk)
+    # the drops do not touch: the 0-1 tension moves the loss 5e7 times less than the
+    # others, so the tolerance is floored at 1e-2 of the largest component as above
+    scale = max(abs(f[0]) for f in fds)
+    for k in range(3):
+        fd, fd2 = fds[k]
+        tol = 1e-4 * max(abs(fd), 1e-2 * scale)
+        print(f"  walls dL/dsigma_{k}: adjoint {gs[k]:.8e} fd {fd:.8e} fd(h/2) {fd2:.8e}")
+        assert abs(fd - fd2) <= tol
+        assert abs(gs[k] - fd) <= tol
+    rng = np.random.default_rng(23)
+    for r in range(2):
+        dirn = np.zeros_like(phi)
+        for p in range(2):
+            dirn[p] = rng.standard_normal(phi[p].shape) * phi[p] * (1 - phi[p])
+        dirn[2] = -(dirn[0] + dirn[1])
+        h = 1e-6
+        fd = (_oracle_loss(cfg, phi + h * dirn, target, steps) -
+              _oracle_loss(cfg, phi - h * dirn, target, steps)) / (2 * h)
+        adj = float((gphi * dirn).sum())
+        print(f"  walls dL/dphi0 . d{r}: adjoint {adj:.8e} fd {fd:.8e}")
         assert abs(adj - fd) <= 1e-4 * abs(fd)
 
 

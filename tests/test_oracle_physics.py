@@ -236,3 +236,39 @@ def test_shear_wave_viscosity(phi_a, rho, tau):
     nu = (mu[0] * phi_a + mu[1] * (1 - phi_a)) / (rho[0] * phi_a + rho[1] * (1 - phi_a))
     # lattice dispersion of the shear mode is O(k^2): 5e-4 at L = 32
     assert abs(rate / (nu * k * k) - 1) < 2e-3
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_step_is_affine_in_the_lagged_fields(walls):
+    """phi^{t-1} and m_phi^{t-1} enter one step only through the Euler time derivatives
+    (Sec. 3: d_t(phi u) in the source term of the phase collision, d_t(m.u) in the
+    pressure and in the second-order flow moments), each linearly: the second difference
+    of the step along either vanishes to round-off, while along u^{t-1} (which also enters
+    F_c and so u^t) it does not."""
+    rng = np.random.default_rng(4)
+    N, ny, nx = 3, 14, 16
+    a = rng.uniform(0.2, 1.0, size=(N, ny, nx))
+    cfg = inputs.base_cfg("D2Q9", nx, ny, 1, N, inputs.random_sigma(N, rng, 0.005, 0.02),
+                          [2.0, 1.5, 1.0], [0.8, 0.7, 0.9], mobility=0.03, eps=3.0)
+    if walls:
+        cfg = dict(cfg, walls=True, contact_cos=[0.4, -0.3])
+    C = O.Config(cfg)
+    st = O.step(C, O.init(C, a / a.sum(0)), 3)
+
+    def second_difference(key, h=1e-3):
+        ds = rng.standard_normal(st[key].shape)
+        out = []
+        for sgn in (-1, 0, 1):
+            s2 = dict(st)
+            s2[key] = st[key] + sgn * h * ds
+            o = O.step(C, s2, 1)
+            out.append(np.concatenate([o[k].ravel() for k in
+                                       ("f", "g", "u_prev", "phi_prev", "mphi_prev")]))
+        return np.abs(out[0] + out[2] - 2 * out[1]).max(), np.abs(out[2] - out[0]).max()
+
+    for key in ("phi_prev", "mphi_prev"):
+        sec, first = second_difference(key)
+        # round-off of outputs of magnitude one: a few hundred units in the last place
+        assert first > 1e-8 and sec <= 1e-13, (key, sec, first)
+    sec, first = second_difference("u_prev")
+    assert sec > 1e-3 * first
