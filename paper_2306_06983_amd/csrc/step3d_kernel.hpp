@@ -15,9 +15,10 @@
 // j_p = sum_i c_i f_{i,p}, and in FP32 the exact rounding residual of phi.  At t = 0 the
 // state is the equilibrium f_i = w_i phi0 of the initial condition: phi = phi0, j = 0.
 //
-// nphase_step3d_kernel: a workgroup of 256 threads owns a TX x TY column tile (one thread
-// per column; 64 x 4 in FP64, 32 x 8 in FP32) and a run of ZR planes in z.  It marches through the run with a three-stage
-// pipeline, one plane per stage and iteration:
+// nphase_step3d_kernel: a workgroup owns a TX x TY column tile (one thread per column:
+// 64 x 8 in FP64 and 32 x 16 in FP32, 512 threads, where the LDS rings of the evolved sets
+// fit one CU; else 64 x 4 and 32 x 8, 256 threads) and a run of ZR planes in z.  It marches
+// through the run with a three-stage pipeline, one plane per stage and iteration:
 //   S1 plane z+2   phi (and Model B pair fractions) on the tile plus a 2-node ring in x,y,
 //                  from the moments, into a ring of LDS planes;
 //   S2 plane z+1   gradients, Laplacians, sources R_p, m_phi on the tile plus a 1-node
@@ -27,10 +28,10 @@
 //                  moment-space collisions, written as (phi, A, D) at the own node, and
 //                  the push of the flow populations (Sec. 2.2, Sec. 3).
 // The own-node results of S2 are kept in registers for the S3 of the next iteration.  The
-// halo is recomputed only in x and y (FP64: 2.1x the phi loads for the 68 x 8 region
-// plane and 1.55x the S2 work for the 66 x 6 inner plane; FP32: 1.69x and 1.33x); in z
-// every plane is computed once per run plus 4 pipeline-fill planes.  The arithmetic is the
-// same as the tile kernel's.
+// halo is recomputed only in x and y (64 x 8: 1.59x the phi loads for the 68 x 12 region
+// plane and 1.29x the S2 work for the 66 x 10 inner plane; 32 x 16: 1.41x and 1.20x; the
+// 256-thread tiles: 2.1x and 1.55x, 1.69x and 1.33x); in z every plane is computed once
+// per run plus 4 pipeline-fill planes.  The arithmetic is the same as the tile kernel's.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -69,14 +70,15 @@ constexpr int n_moments() {
   return NS * 4 + (sizeof(T) == 4 ? NS : 0);
 }
 
-// Column tile and run of the moments pass: 64 x 4 columns, 32 planes.  It marches in z
-// per evolved set with a 3-plane LDS ring of the moment fields (tile + 1-node ring in x,y),
-// so every stored value is read from memory about 1.55 times (the x,y halo) instead of
-// once per neighbour that pulls from it.
-constexpr int M3_TX = 64, M3_TY = 4, M3_ZR = 32;
+// Column tile and run of the moments pass: 64 x 8 columns (512 threads), 32 planes.  It
+// marches in z per evolved set with a 3-plane LDS ring of the moment fields (tile + 1-node
+// ring in x,y: 111 KB in FP64, one workgroup per CU; 55 KB in FP32, two), so every stored
+// value is read from memory about 1.29 times (the x,y halo) instead of once per neighbour
+// that pulls from it.  (64 x 4 measured 5 % slower on this pass in FP64, equal in FP32.)
+constexpr int M3_TX = 64, M3_TY = 8, M3_ZR = 32, M3_NT = M3_TX * M3_TY;
 
 template <typename T, int NS>
-__global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) nphase_moments3d_kernel(const StepArgs<T> a) {
+__global__ void __launch_bounds__(M3_NT, sizeof(T) == 4 ? 4 : 2) nphase_moments3d_kernel(const StepArgs<T> a) {
   using L = Lattice<LAT_D3Q19>;
   constexpr int D = 3, Q = 19, NMR = MR<T>::N;
   constexpr int NF = 7;   // phi, A, D: the fields pulled from neighbours
@@ -128,12 +130,12 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) nphase_momen
   // iteration ahead and written to its ring slot after the compute, so the loads overlap
   // the LDS work.  Positions past a ragged edge (columns no thread owns) wrap like the
   // rest, so every load stays inside the grid.
-  constexpr int PL = (NF * RP + NTHREADS - 1) / NTHREADS;
+  constexpr int PL = (NF * RP + M3_NT - 1) / M3_NT;
   T pre[PL];
   unsigned poff[PL];   // in-plane node of each fetched value (fixed per workgroup)
 #pragma unroll
   for (int j = 0; j < PL; ++j) {
-    const int k = t + j * NTHREADS;
+    const int k = t + j * M3_NT;
     const int r = (k < NF * RP ? k : 0) % RP;
     poff[j] = (unsigned)wrap(tx0 - 1 + r % RX, nx) + (unsigned)nx * (unsigned)wrap(ty0 - 1 + r / RX, ny);
   }
@@ -141,7 +143,7 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) nphase_momen
     const size_t zoff = plane * (size_t)wrap(z, nz);
 #pragma unroll
     for (int j = 0; j < PL; ++j) {
-      const int k = t + j * NTHREADS;
+      const int k = t + j * M3_NT;
       if (k < NF * RP) pre[j] = LD(p * NMR + k / RP, (size_t)poff[j] + zoff);
     }
   };
@@ -149,7 +151,7 @@ __global__ void __launch_bounds__(NTHREADS, sizeof(T) == 4 ? 4 : 2) nphase_momen
     const int sl = slot(z);
 #pragma unroll
     for (int j = 0; j < PL; ++j) {
-      const int k = t + j * NTHREADS;
+      const int k = t + j * M3_NT;
       if (k < NF * RP) s_mr[sl][k / RP][k % RP] = pre[j];
     }
   };

@@ -46,7 +46,6 @@
 namespace nphase {
 
 constexpr int MAXN = 8;
-constexpr int NTHREADS = 256;
 constexpr double NORMAL_EPS = 1e-12;   // |v|^2 > NORMAL_EPS^2 to normalise, else n = 0
 constexpr double PAIR_EPS = 1e-12;     // phi_p + phi_q > PAIR_EPS, else phi_pq = 1/2
 constexpr int MODE_STEP = 0;
