@@ -1,10 +1,14 @@
 // Fused time step of the consistent and conservative N-phase LBM (one kernel per step).
 //
 // Per workgroup: one tile of TX x TY (x TZ) nodes, one node per thread.
-//   stage 1  region = tile + 2-node halo: phi_p = sum_i f_{i,p} (Sec. 3 macroscopic
-//            recovery) for the evolved sets, phi_N = 1 - sum (Sec. 4 intro), and for
-//            Model B the pairwise fractions phi_pq = phi_p/(phi_p + phi_q) (Sec. 2.1);
-//            all into LDS.  Interior threads keep the first moments j_p of their node.
+//   stage 0  the moment form (phi, A, D) of every evolved set on the tile + 3-node halo
+//            into LDS.
+//   stage 1  region = tile + 2-node halo: the pulled populations f_i(x) = f*_i(x - c_i)
+//            rebuilt from the moment form of the upwind neighbours and reduced to
+//            phi_p = sum_i f_{i,p} (Sec. 3 macroscopic recovery), phi_N = 1 - sum
+//            (Sec. 4 intro), and for Model B the pairwise fractions
+//            phi_pq = phi_p/(phi_p + phi_q) (Sec. 2.1); all into LDS.  Interior threads
+//            keep the first moments j_p of their node.
 //   stage 2  tile + 1-node halo: isotropic gradients (Sec. 3 closing paragraph), sources
 //            R_p of Model A / Model B (Sec. 2.1), mass-diffusion flux
 //            m_phi = -M sum_p rho_p (grad phi_p - R_p) (Sec. 2.2), and the antisymmetric
@@ -14,19 +18,20 @@
 //            gravity, u, m, P (Sec. 3), the moment-space collisions of every evolved
 //            phase set and of the flow set in closed form (natural M, diagonal S:
 //            only the first-order rows relax with 1/tau_f for the phase field, only the
-//            second-order rows with the local 1/tau_g for the flow), push-streaming into
-//            the destination buffers, and the history fields u, phi, m_phi.
+//            second-order rows with the local 1/tau_g for the flow); each phase set is
+//            written as its moment form at the node itself, the flow populations are
+//            pushed, and the history fields u and m_phi are written.
 //
 // Storage (SoA, x fastest, V nodes):
-//   f [NS][Q][V]   phase populations.  FP64: f_{i,p}.  FP32: deviations
-//                  f~_{i,p} = f_{i,p} - w_i phi_p^{t-1}(x) from the rest weights of the
-//                  previous-step local order parameter (which is stored anyway); the
-//                  exact rounding residual of phi^{t-1} + sum f~ in FP32 is added to the
-//                  rest deviation f~_0 the node writes, so the stored state keeps its mass.
+//   f [NS][MR::N][V]  moment form of the post-collision phase populations (layout MR
+//                  below): phi, which is also the next step's phi^{t-1}, A and D, and in
+//                  FP32 the exact rounding residual of phi^{t-1} + sum f~ (the rebuilt
+//                  populations are then deviations f~_i = f_i - w_i phi^{t-1} from the rest
+//                  weights of the node's own phi^{t-1}), which the rest population of the
+//                  node carries so that the stored state keeps its mass.
 //   g [Q-1][V]     flow populations i = 1..Q-1 (g_0 feeds no moment used later: P takes
 //                  sum_{i != 0} g_i and c_0 = 0, so it is never stored).
 //   u [D][V]       velocity u^{t-1} (ping-pong: read at radius 1).
-//   pm [NS][V]     phi^{t-1} of the evolved sets (ping-pong: FP32 reads it at radius 2).
 //   mm [D][V]      m_phi^{t-1} (read and written at the own node only: in place).
 //
 // Walls (D2Q9, below row 0 and above row ny - 1, half-way): a population that would be
