@@ -312,7 +312,7 @@ __global__ void __launch_bounds__((Z3Tile<T, (SA ? N : N - 1)>::NT), 2)
 #pragma unroll
     for (int d = 1; d < D; ++d) n2 += v[d] * v[d];
     if (n2 > T(NORMAL_EPS * NORMAL_EPS)) {
-      const T inv = T(1) / sqrt(n2);
+      const T inv = inv_sqrt(n2);
 #pragma unroll
       for (int d = 0; d < D; ++d) v[d] *= inv;
     } else {
