@@ -431,18 +431,23 @@ def test_state64_export():
     s32.close()
 
 
-def test_fp32_adjoint_vs_fp64_adjoint():
+@pytest.mark.parametrize("walls", [False, True])
+def test_fp32_adjoint_vs_fp64_adjoint(walls):
     """The adjoint along the FP32 trajectory (FP32 forward, FP64 adjoint steps on the
-    exported states) against the FP64 adjoint on the 60-step misfit of the oracle test:
+    exported states) against the FP64 adjoint on the 60-step misfit of the oracle test
+    (walls: the two wetting drops with gravity):
     the difference is what FP32 storage does to the gradient, a reported error rather than
     a specified one.  Sanity bars: 1e-3 relative per pair tension (floored at 1e-2 of the
-    largest, as in the oracle test; measured <= 5e-4) and 1e-2 along the phi0 directions
-    (measured ~3e-3: the phi0 derivative lives on the interfaces, where the FP32 state's
-    relative error is largest)."""
+    largest, as in the oracle test; measured <= 5e-4, with walls <= 4e-6) and 1e-2 along
+    the phi0 directions (measured ~3e-3, with walls <= 6e-4: the phi0 derivative lives on
+    the interfaces, where the FP32 state's relative error is largest)."""
     import torch
     from paper_2306_06983_amd.autograd import run_differentiable
     steps = 60
-    cfg, phi, target = _loss_setup("B", steps=steps)
+    if walls:
+        cfg, phi, target = _walled_loss_setup("B", steps, (0.0, -1e-5, 0.0))
+    else:
+        cfg, phi, target = _loss_setup("B", steps=steps)
     tgt = torch.tensor(target, device="cuda:0")
     out = {}
     for prec in ("fp64", "fp32"):
