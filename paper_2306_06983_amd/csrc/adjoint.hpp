@@ -109,7 +109,8 @@ struct Nbr {
   }
 };
 
-// all N order parameters at node y (the last one rebuilt where N - 1 sets are evolved)
+// all N order parameters at node y, as the phi recompute left them (with N - 1 evolved
+// sets it has already rebuilt the last one)
 template <int N>
 __device__ __forceinline__ void phases_at(const AdjArgs& a, long long y, double* ph) {
   for (int p = 0; p < N; ++p) ph[p] = a.F_phi[(long long)p * a.V + y];
