@@ -1,7 +1,7 @@
 """Benchmark of the fused N-phase LBM step on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
-    python bench.py --only spheres_fp64|spheres_fp32|bands_fp32|rti_fp64|rti_fp32
+    python bench.py --only spheres_fp64|spheres_fp32|bands_fp32|rti_fp64|rti_fp32|adjoint_step
                     [--steps K] [--warmup W]
 
 Workload: 512 x 512 periodic D2Q9, N = 4 phases, 40 seeded non-overlapping discs radii
@@ -14,8 +14,8 @@ value = FP64 Model B MLUPS (node updates per second / 1e6); the FP32 form, Model
 the oracle on the host (cpu_baseline) are reported beside it, and (unless --no-extra)
 the 256^3 D3Q19 N = 4 drops (FP64, FP32), the 2048^2 N = 5 layered bands (FP32), the
 walled ternary Rayleigh-Taylor instability of Sec. 4.4 on 256 x 1024 (FP64, FP32; timing
-and the interface locations at T = 1, 2, 3) and the wall time of a differentiable 256^2
-run (forward with checkpoints, adjoint backward).
+and the interface locations at T = 1, 2, 3), the wall time of a differentiable 256^2
+run (forward with checkpoints, adjoint backward) and the adjoint step alone (HIP events).
 `--only NAME` times one of those other workloads alone (for profiling) and prints its
 record instead of the line.  roofline: the step kernel is HBM-bound (no dense contraction); achieved = algorithmic bytes per launch
 (every persisted value read once and written once) / mean launch time measured with
@@ -208,7 +208,53 @@ def time_adjoint(steps=25, ckpt_every=10):
     g64, g32 = grads["fp64"], grads["fp32"]
     out["fp32_dsigma_rel_diff_vs_fp64"] = float(np.max(np.abs(g32 - g64)) /
                                                  max(np.max(np.abs(g64)), 1e-300))
+    out["adjoint_step_kernels"] = [
+        time_adjoint_step("two_discs_256x256_N3_d2q9", cfg, phi),
+        time_adjoint_step("many_discs_512x512_N4_d2q9", *inputs.many_discs())]
     return out
+
+
+def time_adjoint_step(name, cfg, phi, reps=100):
+    """The adjoint step alone (its forward-recompute and reverse kernels, one call of
+    adjoint_step) timed with HIP events on the library's stream over `reps` calls, at a
+    state taken after four forward steps.  Algorithmic bytes per node and step: the state
+    s^t and the adjoint lambda^{t+1} read and lambda^t written, each in the FP64
+    save_state64 layout (3 x its payload); the kernels also write and re-read their
+    per-node intermediates, which these bytes leave out."""
+    import numpy as np
+    import torch
+    from paper_2306_06983_amd import binding as B
+    hdr = 256
+    sim = B.Sim(cfg, "fp64").init(phi)
+    sim.step(4)
+    s0 = sim.save_state64().clone()
+    payload = s0.numel() - hdr
+    gen = torch.Generator(device="cpu").manual_seed(0)
+    lam = torch.zeros_like(s0)
+    lam[hdr:].view(torch.float64).copy_(
+        torch.randn(payload // 8, generator=gen, dtype=torch.float64))
+    out = torch.zeros_like(s0)
+    ws = sim.adjoint_workspace()
+    sim.adjoint_sigma(ws, reset=True, read=False)
+    for _ in range(3):
+        sim.adjoint_step(s0, lam, out, ws)
+    stream = sim.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        sim.adjoint_step(s0, lam, out, ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    finite = bool(torch.isfinite(out[hdr:].view(torch.float64)).all().item())
+    sim.close()
+    V = int(np.prod(phi.shape[1:]))
+    nbytes = 3 * payload
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"workload": name, "ms_per_adjoint_step": round(ms, 4),
+            "bytes_per_node_step": nbytes // V, "achieved_GBs": round(gbs, 1),
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "finite": finite}
 
 
 def time_oracle(cfg, phi, max_seconds=15.0, max_steps=200):
@@ -270,8 +316,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the 3D, 2048^2 and adjoint workloads reported beside the line")
     ap.add_argument("--only", choices=["spheres_fp64", "spheres_fp32", "bands_fp32",
-                                       "rti_fp64", "rti_fp32"],
-                    help="time only this other workload and print its record")
+                                       "rti_fp64", "rti_fp32", "adjoint_step"],
+                    help="time only this other workload (adjoint_step: the adjoint step "
+                         "alone on the 512^2 workload, --steps calls) and print its record")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 256 MiB ten times (reference "
                          "for the memory traffic counters)")
@@ -304,6 +351,10 @@ def main():
         return time_extra(c5, p5, prec, steps, warm, 2, 9, c5["n_phases"] - 1,
                           "ternary_rti_walls_256x1024_N3_d2q9")
 
+    if args.only == "adjoint_step":
+        print(json.dumps(time_adjoint_step("many_discs_512x512_N4_d2q9", *inputs.many_discs(),
+                                           reps=args.steps)))
+        return 0
     if args.only:
         kind, prec = args.only.split("_")
         rec = {"spheres": spheres, "bands": bands, "rti": rti}[kind](prec, args.steps,

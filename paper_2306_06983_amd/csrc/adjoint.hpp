@@ -116,6 +116,15 @@ __device__ __forceinline__ void phases_at(const AdjArgs& a, long long y, double*
   for (int p = 0; p < N; ++p) ph[p] = a.F_phi[(long long)p * a.V + y];
 }
 
+// Block of the grid a workgroup takes.  Workgroup ids are dealt round-robin over the 8
+// XCDs; each XCD is given a contiguous range of blocks instead, so that the neighbour rows
+// a stencil gathers were read by blocks of the same XCD and sit in its L2.  A bijection on
+// [0, nb).
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int q = nb / 8, r8 = nb % 8, xcd = b % 8, loc = b / 8;
+  return xcd * q + (xcd < r8 ? xcd : r8) + loc;
+}
+
 __device__ __forceinline__ double gsecond(double p) {   // d/dphi g'(phi) = 2 - 12 phi + 12 phi^2
   return 2.0 - 12.0 * p + 12.0 * p * p;
 }
@@ -125,7 +134,7 @@ template <int LAT, int N, bool SA>
 __global__ void __launch_bounds__(256) adj_fwd1(const AdjArgs a) {
   using L = Lattice<LAT>;
   constexpr int Q = L::Q, D = L::D, NS = SA ? N : N - 1;
-  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long x = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (x >= a.V) return;
   const long long V = a.V;
   double rest = 0.0;
@@ -154,7 +163,7 @@ __global__ void __launch_bounds__(256) adj_fwd2(const AdjArgs a) {
   using L = Lattice<LAT>;
   constexpr int Q = L::Q, D = L::D, NP = N * (N - 1) / 2;
   constexpr int NW = (D == 3) ? 3 : 1;
-  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long x = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (x >= a.V) return;
   const long long V = a.V;
   Nbr<L> nb(x, a.nx, a.ny, a.nz, a.walls);
@@ -262,7 +271,7 @@ __global__ void __launch_bounds__(256) adj_fwd3(const AdjArgs a) {
   using L = Lattice<LAT>;
   constexpr int Q = L::Q, D = L::D;
   constexpr int NW = (D == 3) ? 3 : 1;
-  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long x = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (x >= a.V) return;
   const long long V = a.V;
   Nbr<L> nb(x, a.nx, a.ny, a.nz, a.walls);
@@ -302,7 +311,7 @@ __global__ void __launch_bounds__(256) adj_rev1(const AdjArgs a) {
   // per-block partials: dL/dsigma_pq of every pair, then dL/drho_bar (gravity reference)
   constexpr int NACC = NPAIR + 1;
   __shared__ double red[NACC][256];
-  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long x = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const long long V = a.V;
   double sig_loc[NACC];
   for (int k = 0; k < NACC; ++k) sig_loc[k] = 0.0;
@@ -651,7 +660,7 @@ __global__ void __launch_bounds__(256) adj_rev1(const AdjArgs a) {
     __syncthreads();
   }
   if (threadIdx.x == 0)
-    for (int k = 0; k < NACC; ++k) a.sig_partial[k * a.nblk + blockIdx.x] += red[k][0];
+    for (int k = 0; k < NACC; ++k) a.sig_partial[k * a.nblk + xcd_block(blockIdx.x, gridDim.x)] += red[k][0];
 }
 
 
@@ -662,7 +671,7 @@ __global__ void __launch_bounds__(256) adj_rev2(const AdjArgs a) {
   using L = Lattice<LAT>;
   constexpr int Q = L::Q, D = L::D, NP = N * (N - 1) / 2;
   constexpr int NW = (D == 3) ? 3 : 1;
-  const long long y = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long y = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (y >= a.V) return;
   const long long V = a.V;
   Nbr<L> nb(y, a.nx, a.ny, a.nz, a.walls);
@@ -816,7 +825,7 @@ template <int LAT, int N, bool SA, int MODEL>
 __global__ void __launch_bounds__(256) adj_rev3(const AdjArgs a) {
   using L = Lattice<LAT>;
   constexpr int Q = L::Q, D = L::D, NS = SA ? N : N - 1, NP = N * (N - 1) / 2;
-  const long long z = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long z = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (z >= a.V) return;
   const long long V = a.V;
   Nbr<L> nb(z, a.nx, a.ny, a.nz, a.walls);
