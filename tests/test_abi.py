@@ -44,6 +44,19 @@ def test_workspace_bytes_model(lib):
     assert rc == B.NPHASE_OK and n32 < n
 
 
+def test_largest_grid_sized_without_overflow(lib):
+    """65535 x 65537 = 2^32 - 65537 nodes, just below the limit: accepted, and the
+    workspace size is computed in 64 bits (no wrap-around of the 32-bit node count)."""
+    cfg, _ = inputs.two_discs()
+    p = B.make_params(cfg)
+    p.nx, p.ny = 65535, 65537
+    rc, n = _ws(lib, p)
+    assert rc == B.NPHASE_OK
+    V, NS, Q, d = 65535 * 65537, 2, 9, 2
+    state = 2 * (NS * (1 + 2 * d) + (Q - 1) + d) + d
+    assert n >= state * V * 8
+
+
 @pytest.mark.parametrize("precision,b,nmr,nm", [("fp64", 8, 7, 4), ("fp32", 4, 8, 5)])
 def test_workspace_bytes_d3q19(lib, precision, b, nmr, nm):
     # D3Q19 state: the phase field in moment form (phi, A, D per set; FP32 also the
@@ -80,6 +93,9 @@ def test_workspace_bytes_d3q19(lib, precision, b, nmr, nm):
     (lambda p: (setattr(p, "walls", 1), p.contact_cos.__setitem__(0, float("nan"))),
      B.NPHASE_EINVAL),
     (lambda p: (setattr(p, "walls", 1), setattr(p, "ny", 1)), B.NPHASE_EINVAL),
+    (lambda p: setattr(p, "pair_normals", 2), B.NPHASE_EINVAL),
+    # element offsets are 32-bit: at most 2^32 - 1 nodes
+    (lambda p: (setattr(p, "nx", 65536), setattr(p, "ny", 65536)), B.NPHASE_EINVAL),
 ])
 def test_invalid_parameters_rejected(lib, mutate, code):
     cfg, _ = inputs.two_discs()
