@@ -120,7 +120,9 @@ constexpr size_t step2d_lds_bytes() {
 // waves per CU of 32 x 8, with less halo recomputed per node: FP64 where the LDS of 32 x 8
 // already limits a CU to two workgroups (8 waves) and 32 x 16 fits one (measured 5 % on
 // 512^2 N = 4), FP32 where two 32 x 16 workgroups fit, with registers bounded for 4 waves
-// per SIMD (7-8 % on 512^2 N = 4, 5 % on the 256 x 1024 N = 3 walled box).  N > 4 keeps
+// per SIMD (7-8 % on 512^2 N = 4, 5 % on the 256 x 1024 N = 3 walled box); FP32 takes
+// 32 x 32 (1024 threads) where that single workgroup still fits one CU's LDS, the same 16
+// waves with less halo (3 % on the 512^2 N = 4 Model B step, equal elsewhere).  N > 4 keeps
 // 32 x 8: its registers do not allow those waves (a 2048^2 FP32 N = 5 step lost 35 % to a
 // tall tile at fewer waves per CU).
 template <typename T, int LAT, int N, bool SA, int MODEL>
@@ -131,10 +133,14 @@ struct StepTile {
   static constexpr bool TALL32 = sizeof(T) == 4 &&
                                  step2d_lds_bytes<T, N, SA, MODEL, 16>() <= (size_t)163840 / 2;
   static constexpr bool TALL = LAT == LAT_D2Q9 && N <= 4 && (TALL64 || TALL32);
-  // FP32 tall tiles: registers for 4 waves per SIMD (two workgroups per CU)
+  // FP32 tall tiles: registers for 4 waves per SIMD (two 512-thread or one 1024-thread
+  // workgroup per CU)
   static constexpr int MINW = (TALL && sizeof(T) == 4) ? 4 : 1;
   static constexpr int TX = TileShape<LAT>::TX;
-  static constexpr int TY = TALL ? 16 : TileShape<LAT>::TY;
+  // FP32: 32 x 32 (1024 threads, one workgroup of 16 waves per CU) where its LDS fits
+  static constexpr bool SQ32 = TALL && sizeof(T) == 4 &&
+                               step2d_lds_bytes<T, N, SA, MODEL, 32>() <= (size_t)163840;
+  static constexpr int TY = SQ32 ? 32 : (TALL ? 16 : TileShape<LAT>::TY);
   static constexpr int TZ = TileShape<LAT>::TZ;
   static constexpr int NT = TX * TY * TZ;
 };
