@@ -122,7 +122,10 @@ constexpr size_t step2d_lds_bytes() {
 // 512^2 N = 4), FP32 where two 32 x 16 workgroups fit, with registers bounded for 4 waves
 // per SIMD (7-8 % on 512^2 N = 4, 5 % on the 256 x 1024 N = 3 walled box); FP32 takes
 // 32 x 32 (1024 threads) where that single workgroup still fits one CU's LDS, the same 16
-// waves with less halo (3 % on the 512^2 N = 4 Model B step, equal elsewhere).  N > 4 keeps
+// waves with less halo (3 % on the 512^2 N = 4 Model B step, equal elsewhere).  FP64 with
+// the LDS of two 32 x 16 workgroups per CU (N <= 3) takes them with registers bounded for
+// 4 waves per SIMD, 16 waves per CU instead of the 12 of three 32 x 8 ones (17-18 % on the
+// 256 x 1024 N = 3 walled box).  N > 4 keeps
 // 32 x 8: its registers do not allow those waves (a 2048^2 FP32 N = 5 step lost 35 % to a
 // tall tile at fewer waves per CU).
 template <typename T, int LAT, int N, bool SA, int MODEL>
@@ -132,10 +135,13 @@ struct StepTile {
                                  step2d_lds_bytes<T, N, SA, MODEL, 16>() <= (size_t)163840;
   static constexpr bool TALL32 = sizeof(T) == 4 &&
                                  step2d_lds_bytes<T, N, SA, MODEL, 16>() <= (size_t)163840 / 2;
-  static constexpr bool TALL = LAT == LAT_D2Q9 && N <= 4 && (TALL64 || TALL32);
-  // FP32 tall tiles: registers for 4 waves per SIMD (two 512-thread or one 1024-thread
-  // workgroup per CU)
-  static constexpr int MINW = (TALL && sizeof(T) == 4) ? 4 : 1;
+  // FP64 with a small LDS footprint (N <= 3): two 32 x 16 workgroups per CU
+  static constexpr bool TALL64W = sizeof(T) == 8 && !TALL64 &&
+                                  step2d_lds_bytes<T, N, SA, MODEL, 16>() <= (size_t)163840 / 2;
+  static constexpr bool TALL = LAT == LAT_D2Q9 && N <= 4 && (TALL64 || TALL64W || TALL32);
+  // registers for 4 waves per SIMD: FP32 tall tiles (two 512-thread or one 1024-thread
+  // workgroup per CU) and the FP64 pair of 32 x 16 workgroups
+  static constexpr int MINW = (TALL && (sizeof(T) == 4 || TALL64W)) ? 4 : 1;
   static constexpr int TX = TileShape<LAT>::TX;
   // FP32: 32 x 32 (1024 threads, one workgroup of 16 waves per CU) where its LDS fits
   static constexpr bool SQ32 = TALL && sizeof(T) == 4 &&
