@@ -1,7 +1,7 @@
 """Benchmark of the fused N-phase LBM step on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
-    python bench.py --only spheres_fp64|spheres_fp32|bands_fp32|rti_fp64|rti_fp32|adjoint_step
+    python bench.py --only spheres_fp64|spheres_fp32|bands_fp32|bands_fp64|rti_fp64|rti_fp32|adjoint_step
                     [--steps K] [--warmup W]
 
 Workload: 512 x 512 periodic D2Q9, N = 4 phases, 40 seeded non-overlapping discs radii
@@ -12,7 +12,7 @@ launch), inputs resident in HBM.  Prints ONE JSON line.
 
 value = FP64 Model B MLUPS (node updates per second / 1e6); the FP32 form, Model A and
 the oracle on the host (cpu_baseline) are reported beside it, and (unless --no-extra)
-the 256^3 D3Q19 N = 4 drops (FP64, FP32), the 2048^2 N = 5 layered bands (FP32), the
+the 256^3 D3Q19 N = 4 drops (FP64, FP32), the 2048^2 N = 5 layered bands (FP32, FP64), the
 walled ternary Rayleigh-Taylor instability of Sec. 4.4 on 256 x 1024 (FP64, FP32; timing
 and the interface locations at T = 1, 2, 3), the wall time of a differentiable 256^2
 run (forward with checkpoints, adjoint backward) and the adjoint step alone (HIP events).
@@ -315,7 +315,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the 3D, 2048^2 and adjoint workloads reported beside the line")
-    ap.add_argument("--only", choices=["spheres_fp64", "spheres_fp32", "bands_fp32",
+    ap.add_argument("--only", choices=["spheres_fp64", "spheres_fp32", "bands_fp32", "bands_fp64",
                                        "rti_fp64", "rti_fp32", "adjoint_step"],
                     help="time only this other workload (adjoint_step: the adjoint step "
                          "alone on the 512^2 workload, --steps calls) and print its record")
@@ -438,7 +438,8 @@ def main():
     if not args.no_extra:
         line["other_workloads"] = [spheres("fp64", 100, 10), spheres("fp32", 100, 10),
                                    spheres("fp64", 100, 10, chain=True),
-                                   bands("fp32", 500, 50), rti("fp64", 2000, 200),
+                                   bands("fp32", 500, 50), bands("fp64", 200, 20),
+                                   rti("fp64", 2000, 200),
                                    rti("fp32", 2000, 200)]
         line["rti_ternary_diagnostics"] = {"fp64": rti_diagnostics("fp64"),
                                            "fp32": rti_diagnostics("fp32")}

@@ -125,9 +125,10 @@ constexpr size_t step2d_lds_bytes() {
 // waves with less halo (3 % on the 512^2 N = 4 Model B step, equal elsewhere).  FP64 with
 // the LDS of two 32 x 16 workgroups per CU (N <= 3) takes them with registers bounded for
 // 4 waves per SIMD, 16 waves per CU instead of the 12 of three 32 x 8 ones (17-18 % on the
-// 256 x 1024 N = 3 walled box).  N > 4 keeps
-// 32 x 8: its registers do not allow those waves (a 2048^2 FP32 N = 5 step lost 35 % to a
-// tall tile at fewer waves per CU).
+// 256 x 1024 N = 3 walled box).  FP64 N = 5, whose 32 x 8 LDS leaves a CU one 4-wave
+// workgroup, takes 32 x 16 (one 8-wave workgroup: 1.35-1.4x on a 2048^2 N = 5 step); FP64
+// N = 6 does not fit 32 x 16.  FP32 N > 4 keeps 32 x 8: its registers do not allow those
+// waves (a 2048^2 FP32 N = 5 step lost 35 % to a tall tile at fewer waves per CU).
 template <typename T, int LAT, int N, bool SA, int MODEL>
 struct StepTile {
   static constexpr bool TALL64 = sizeof(T) == 8 &&
@@ -138,7 +139,8 @@ struct StepTile {
   // FP64 with a small LDS footprint (N <= 3): two 32 x 16 workgroups per CU
   static constexpr bool TALL64W = sizeof(T) == 8 && !TALL64 &&
                                   step2d_lds_bytes<T, N, SA, MODEL, 16>() <= (size_t)163840 / 2;
-  static constexpr bool TALL = LAT == LAT_D2Q9 && N <= 4 && (TALL64 || TALL64W || TALL32);
+  static constexpr bool TALL = LAT == LAT_D2Q9 && (N <= 4 || sizeof(T) == 8) &&
+                               (TALL64 || TALL64W || TALL32);
   // registers for 4 waves per SIMD: FP32 tall tiles (two 512-thread or one 1024-thread
   // workgroup per CU) and the FP64 pair of 32 x 16 workgroups
   static constexpr int MINW = (TALL && (sizeof(T) == 4 || TALL64W)) ? 4 : 1;
