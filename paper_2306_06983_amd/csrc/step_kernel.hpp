@@ -127,8 +127,10 @@ constexpr size_t step2d_lds_bytes() {
 // 4 waves per SIMD, 16 waves per CU instead of the 12 of three 32 x 8 ones (17-18 % on the
 // 256 x 1024 N = 3 walled box).  FP64 N = 5, whose 32 x 8 LDS leaves a CU one 4-wave
 // workgroup, takes 32 x 16 (one 8-wave workgroup: 1.35-1.4x on a 2048^2 N = 5 step); FP64
-// N = 6 does not fit 32 x 16.  FP32 N > 4 keeps 32 x 8: its registers do not allow those
-// waves (a 2048^2 FP32 N = 5 step lost 35 % to a tall tile at fewer waves per CU).
+// N = 6 does not fit 32 x 16; its Model A takes 32 x 12 (6 waves: 1.22x on a 1024^2 N = 6
+// step; Model B spills at the register bound of 384 threads and loses 31 %).  FP32 N > 4
+// keeps 32 x 8: its registers do not allow those waves (a 2048^2 FP32 N = 5 step lost 35 %
+// to a tall tile at fewer waves per CU).
 template <typename T, int LAT, int N, bool SA, int MODEL>
 struct StepTile {
   static constexpr bool TALL64 = sizeof(T) == 8 &&
@@ -148,7 +150,12 @@ struct StepTile {
   // FP32: 32 x 32 (1024 threads, one workgroup of 16 waves per CU) where its LDS fits
   static constexpr bool SQ32 = TALL && sizeof(T) == 4 &&
                                step2d_lds_bytes<T, N, SA, MODEL, 32>() <= (size_t)163840;
-  static constexpr int TY = SQ32 ? 32 : (TALL ? 16 : TileShape<LAT>::TY);
+  // FP64 Model A with five evolved sets (N = 6, or N = 5 solving all): 32 x 12 (384
+  // threads) where it fits one CU's LDS, 6 waves instead of the 4 of 32 x 8
+  static constexpr bool T12 = LAT == LAT_D2Q9 && sizeof(T) == 8 && MODEL == MODEL_A && !TALL &&
+                              step2d_lds_bytes<T, N, SA, MODEL, 8>() > (size_t)163840 / 2 &&
+                              step2d_lds_bytes<T, N, SA, MODEL, 12>() <= (size_t)163840;
+  static constexpr int TY = SQ32 ? 32 : (TALL ? 16 : (T12 ? 12 : TileShape<LAT>::TY));
   static constexpr int TZ = TileShape<LAT>::TZ;
   static constexpr int NT = TX * TY * TZ;
 };

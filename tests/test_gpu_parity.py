@@ -41,6 +41,7 @@ CASES = {
     "d2q9_B_N2_36x20": (lambda: ragged_discs(36, 20, N=2, count=1), 150),
     "d2q9_B_N5_60x44": (lambda: ragged_discs(60, 44, N=5, count=4), 100),
     "d2q9_B_N6_64x48": (lambda: ragged_discs(64, 48, N=6, count=5), 60),
+    "d2q9_A1_N6_50x39": (lambda: ragged_discs(50, 39, N=6, model="A", count=5), 60),
     "d2q9_B_tiny_3x16": (lambda: _tiny_band(3, 16), 80),
     "d2q9_B_tile_exact_64x32": (lambda: ragged_discs(64, 32, N=3, seed=11), 120),
     "d3q19_B_25x19x14": (lambda: ragged_spheres(25, 19, 14), 30),
