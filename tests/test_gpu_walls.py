@@ -82,6 +82,11 @@ CASES = {
     "walls_A1_N3_33x9": (lambda: _discs(33, 9, model="A", count=2, rmin=2.5, rmax=3.5,
                                         cos_pN=[-0.2, 0.6]), 120),
     "walls_B_N3_mixture_7x2": (lambda: _random_mixture(7, 2), 40),
+    # the 32 x 16 (FP64 N = 5) and 32 x 12 (FP64 Model A, N = 6) tiles against both walls
+    "walls_B_N5_44x29": (lambda: _discs(44, 29, N=5, count=4, rmin=3.0, rmax=4.5,
+                                        cos_pN=[0.3, -0.2, 0.4, -0.5]), 60),
+    "walls_A1_N6_52x29": (lambda: _discs(52, 29, N=6, model="A", count=5, rmin=3.0, rmax=3.5,
+                                         cos_pN=[0.2, -0.4, 0.5, -0.1, 0.3]), 50),
     "walls3d_B_N4_21x17x19": (lambda: _spheres(21, 17, 19, cos_pN=[0.4, -0.3, 0.2]), 30),
     "walls3d_A2_N3_solve_all_gravity_18x14x37": (
         lambda: _spheres(18, 14, 37, N=3, model="A", model_a_n=2, solve_all=True,
