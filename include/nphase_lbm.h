@@ -143,6 +143,11 @@ int nphase_lbm_init(nphase_lbm_t h, const double *phi0_dev);
  * the other; phase populations pulled from the moment form, flow populations pushed): one
  * fused kernel per step on D2Q9; on D3Q19 a moments kernel (pulls the phase populations and
  * reduces them to phi_p, j_p) followed by the fused z-marching collide-and-stream kernel.
+ * The step from the initial state runs alone; the others are issued as multi-step HIP
+ * graphs of 64, 32, ..., 2 steps (binary decomposition of the count, at most one single
+ * step left over), recorded once per handle on a private stream (default priority) and
+ * launched on the handle's stream; init and load_state discard them.  The graphs hold
+ * kernel nodes only.  Results are bitwise those of single steps.
  * Asynchronous on the stream. */
 int nphase_lbm_step(nphase_lbm_t h, int64_t nsteps);
 
@@ -176,8 +181,13 @@ int nphase_lbm_time(nphase_lbm_t h, int64_t *t_host);
 /* Full state (populations, history fields, step parity and time) for checkpointing:
  * save copies it into a caller device buffer of state_bytes bytes, load restores it.
  * Both synchronise the stream once for the 256-byte header (host <-> device), then
- * enqueue the payload copies on the stream.  load returns EINVAL for a buffer that
- * save did not write. */
+ * enqueue the payload copies on the stream.  The header records the layout (its own
+ * magic for save and for save_state64), the payload size and the configuration (lattice,
+ * precision, N, solve_all, grid, walls, model, Model A exponent, pair normals).  load
+ * reads only the header first and returns EINVAL, before any payload copy and with the
+ * handle unchanged, for a buffer that save did not write or that was written for another
+ * configuration (a save_state64 export included).  The buffer must hold at least the 256
+ * header bytes. */
 int nphase_lbm_state_bytes(nphase_lbm_t h, size_t *bytes_host);
 int nphase_lbm_save_state(nphase_lbm_t h, void *state_dev);
 int nphase_lbm_load_state(nphase_lbm_t h, const void *state_dev);

@@ -36,6 +36,8 @@ class NPhaseRun(torch.autograd.Function):
         phiT = sim.fields()[0]
         ctx.sim, ctx.ckpts, ctx.steps = sim, ckpts, steps
         ctx.N = cfg["n_phases"]
+        # the gradient of the pair tensions goes back where they came from
+        ctx.sigma_device, ctx.sigma_dtype = sigma_pairs.device, sigma_pairs.dtype
         return phiT
 
     @staticmethod
@@ -61,12 +63,15 @@ class NPhaseRun(torch.autograd.Function):
         dsig = sim.adjoint_sigma(ws, reset=True)
         N = ctx.N
         pairs = [dsig[p, q] for p in range(N) for q in range(p + 1, N)]
-        dpairs = torch.tensor(pairs, dtype=torch.float64)
+        dpairs = torch.tensor(pairs, dtype=torch.float64).to(device=ctx.sigma_device,
+                                                              dtype=ctx.sigma_dtype)
         return dphi0, dpairs, None, None, None, None
 
 
 def run_differentiable(cfg, phi0, sigma_pairs, steps, ckpt_every=50, precision="fp64"):
     """Phase fields [N, *grid] after `steps` steps, differentiable w.r.t. phi0 and the pair
-    tensions (on phi0's CUDA device; gravity must be zero).  precision "fp64" or "fp32"
-    (the forward's storage and arithmetic; the adjoint steps are FP64)."""
+    tensions sigma_pairs (on phi0's CUDA device; sigma_pairs may live on the host or on
+    the device, and its gradient is returned there).  Walls and gravity are covered (the
+    gravity reference density depends on phi0 and enters dL/dphi0).  precision "fp64" or
+    "fp32" (the forward's storage and arithmetic; the adjoint steps are FP64)."""
     return NPhaseRun.apply(phi0, sigma_pairs, cfg, int(steps), int(ckpt_every), precision)

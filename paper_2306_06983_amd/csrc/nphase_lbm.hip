@@ -44,6 +44,10 @@ struct nphase_lbm_s {
   std::string err;
   StepArgs<double> a64[2];
   StepArgs<float> a32[2];
+  // multi-step graphs: gx[k][side] runs 2^(k+1) steps starting from buffer `side`
+  // (recorded on the private stream `cap`, launched on the caller's stream)
+  hipStream_t cap = nullptr;
+  hipGraphExec_t gx[6][2] = {};
 };
 
 namespace {
@@ -222,25 +226,67 @@ void fill_args(nphase_lbm_t h, StepArgs<T>* out) {
   }
 }
 
+// recorded graphs bake the kernel arguments in: drop them whenever the arguments change
+void drop_graphs(nphase_lbm_t h) {
+  for (auto& row : h->gx)
+    for (auto& g : row)
+      if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+}
+
 void refresh_args(nphase_lbm_t h) {
+  drop_graphs(h);
   if (h->prec == NPHASE_FP64) fill_args<double>(h, h->a64);
   else fill_args<float>(h, h->a32);
 }
 
-hipError_t launch(nphase_lbm_t h, int mode, int side) {
+// one step (or the fields pass) from buffer `side`; `first` marks the step from the
+// initial equilibrium
+hipError_t launch_on(nphase_lbm_t h, int mode, int side, bool first, hipStream_t s) {
   const int N = h->N, sa = h->prm.solve_all, model = step_model(h->prm);
   if (h->prec == NPHASE_FP64) {
     StepArgs<double> a = h->a64[side];
-    a.first = h->t == 0;
+    a.first = first;
     if (h->lat == NPHASE_D2Q9)
-      return launch_step<double, LAT_D2Q9>(N, sa, model, mode, a, h->ntiles, h->stream);
-    return launch_step<double, LAT_D3Q19>(N, sa, model, mode, a, h->ntiles, h->stream);
+      return launch_step<double, LAT_D2Q9>(N, sa, model, mode, a, h->ntiles, s);
+    return launch_step<double, LAT_D3Q19>(N, sa, model, mode, a, h->ntiles, s);
   }
   StepArgs<float> a = h->a32[side];
-  a.first = h->t == 0;
+  a.first = first;
   if (h->lat == NPHASE_D2Q9)
-    return launch_step<float, LAT_D2Q9>(N, sa, model, mode, a, h->ntiles, h->stream);
-  return launch_step<float, LAT_D3Q19>(N, sa, model, mode, a, h->ntiles, h->stream);
+    return launch_step<float, LAT_D2Q9>(N, sa, model, mode, a, h->ntiles, s);
+  return launch_step<float, LAT_D3Q19>(N, sa, model, mode, a, h->ntiles, s);
+}
+
+hipError_t launch(nphase_lbm_t h, int mode, int side) {
+  return launch_on(h, mode, side, h->t == 0, h->stream);
+}
+
+// The graph of 2^(k+1) steps from buffer `side` (none of them the first step), recorded
+// once on the private stream and kept until the arguments change.  An even number of
+// steps ends on the buffer it started from.
+hipError_t step_graph(nphase_lbm_t h, int k, int side, hipGraphExec_t* out) {
+  if (h->gx[k][side]) { *out = h->gx[k][side]; return hipSuccess; }
+  hipError_t e;
+  if (!h->cap) {
+    e = hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+  }
+  e = hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  const int n = 2 << k;
+  hipError_t el = hipSuccess;
+  for (int j = 0; j < n && el == hipSuccess; ++j) el = launch_on(h, MODE_STEP, side ^ (j & 1), false, h->cap);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(h->cap, &g);
+  if (el != hipSuccess || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return el != hipSuccess ? el : e;
+  }
+  e = hipGraphInstantiate(&h->gx[k][side], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) { h->gx[k][side] = nullptr; return e; }
+  *out = h->gx[k][side];
+  return hipSuccess;
 }
 
 template <typename T, int LAT>
@@ -370,7 +416,27 @@ int nphase_lbm_step(nphase_lbm_t h, int64_t nsteps) {
   if (rc) return rc;
   if (!h->inited) { h->err = "step before init"; return NPHASE_ESTATE; }
   if (nsteps < 0) { h->err = "nsteps < 0"; return NPHASE_EINVAL; }
-  for (int64_t k = 0; k < nsteps; ++k) {
+  int64_t left = nsteps;
+  // the step from the initial equilibrium runs alone (it reads the initial moment form)
+  if (left > 0 && h->t == 0) {
+    HIPCHK(launch(h, MODE_STEP, h->cur), "step kernel");
+    h->cur ^= 1;
+    h->t += 1;
+    left -= 1;
+  }
+  // the rest as multi-step graphs of 64, 32, ..., 2 steps (binary decomposition), then
+  // at most one single step
+  for (int k = 5; k >= 0; --k) {
+    const int64_t n = 2 << k;
+    while (left >= n) {
+      hipGraphExec_t g = nullptr;
+      HIPCHK(step_graph(h, k, h->cur, &g), "step graph");
+      HIPCHK(hipGraphLaunch(g, h->stream), "step graph launch");
+      h->t += n;
+      left -= n;
+    }
+  }
+  if (left > 0) {
     HIPCHK(launch(h, MODE_STEP, h->cur), "step kernel");
     h->cur ^= 1;
     h->t += 1;
@@ -501,18 +567,57 @@ int nphase_lbm_state_bytes(nphase_lbm_t h, size_t* bytes_host) {
   return NPHASE_OK;
 }
 
+// 256-byte header of a state buffer: which layout it holds, the configuration it was
+// written for, the payload size, the time and the gravity reference density.  load_state
+// accepts only a buffer whose header matches the handle in every field.
+constexpr int64_t MAGIC_STATE = 0x4e5048415345'4d46;    // moment-form state (save_state)
+constexpr int64_t MAGIC_STATE64 = 0x4e5048415345'3634;  // FP64 populations (save_state64)
+
 struct StateHeader {
+  int64_t magic;
   int64_t t;
   double rho_bar;
-  int64_t magic;
+  uint64_t payload_bytes;
+  int32_t lattice, precision, n_phases, solve_all;
+  int32_t nx, ny, nz, walls;
+  int32_t model, model_a_n, pair_normals, pad;
 };
+static_assert(sizeof(StateHeader) <= ALIGN, "state header fits its 256 bytes");
 
-// 256-byte header of a state buffer (time, gravity reference density, magic)
-static int put_header(nphase_lbm_t h, void* state_dev) {
+static StateHeader header_of(nphase_lbm_t h, int64_t magic, uint64_t payload) {
+  StateHeader hd;
+  std::memset(&hd, 0, sizeof(hd));
+  const nphase_lbm_params& p = h->prm;
+  hd.magic = magic;
+  hd.t = h->t;
+  hd.rho_bar = h->rho_bar;
+  hd.payload_bytes = payload;
+  hd.lattice = p.lattice; hd.precision = p.precision; hd.n_phases = p.n_phases;
+  hd.solve_all = p.solve_all; hd.nx = p.nx; hd.ny = p.ny; hd.nz = p.nz; hd.walls = p.walls;
+  hd.model = p.model; hd.model_a_n = p.model_a_n; hd.pair_normals = p.pair_normals;
+  return hd;
+}
+
+// every field that fixes the payload's layout and meaning must agree (t and rho_bar are
+// the values being restored)
+static const char* header_mismatch(const StateHeader& got, const StateHeader& want) {
+  if (got.magic == MAGIC_STATE64) return "an FP64 population export (save_state64), not a state buffer";
+  if (got.magic != want.magic) return "not a state buffer (bad magic)";
+  if (got.payload_bytes != want.payload_bytes) return "state payload size differs from this handle's";
+  if (got.lattice != want.lattice) return "state written for another lattice";
+  if (got.precision != want.precision) return "state written for another precision";
+  if (got.n_phases != want.n_phases || got.solve_all != want.solve_all)
+    return "state written for another phase count or solve_all setting";
+  if (got.nx != want.nx || got.ny != want.ny || got.nz != want.nz) return "state written for another grid";
+  if (got.walls != want.walls) return "state written for another boundary setting";
+  if (got.model != want.model || got.model_a_n != want.model_a_n || got.pair_normals != want.pair_normals)
+    return "state written for another model";
+  return nullptr;
+}
+
+static int put_header(nphase_lbm_t h, void* state_dev, int64_t magic, uint64_t payload) {
   static thread_local StateHeader hdr;
-  hdr.t = h->t;
-  hdr.rho_bar = h->rho_bar;
-  hdr.magic = 0x4e5048415345;
+  hdr = header_of(h, magic, payload);
   HIPCHK(hipMemcpyAsync(state_dev, &hdr, sizeof(hdr), hipMemcpyHostToDevice, h->stream), "save header");
   HIPCHK(hipStreamSynchronize(h->stream), "save header sync");
   return NPHASE_OK;
@@ -524,8 +629,8 @@ int nphase_lbm_save_state(nphase_lbm_t h, void* state_dev) {
   if (!state_dev) { h->err = "state buffer is NULL"; return NPHASE_EINVAL; }
   if (!h->inited) { h->err = "save before init"; return NPHASE_ESTATE; }
   size_t parts[4];
-  state_payload(h, parts);
-  rc = put_header(h, state_dev);
+  const size_t payload = state_payload(h, parts);
+  rc = put_header(h, state_dev, MAGIC_STATE, payload);
   if (rc) return rc;
   char* q = (char*)state_dev + ALIGN;
   const void* src[4] = {h->f[h->cur], h->g[h->cur], h->u[h->cur], h->mm};
@@ -541,11 +646,16 @@ int nphase_lbm_load_state(nphase_lbm_t h, const void* state_dev) {
   if (rc) return rc;
   if (!state_dev) { h->err = "state buffer is NULL"; return NPHASE_EINVAL; }
   size_t parts[4];
-  state_payload(h, parts);
+  const size_t payload = state_payload(h, parts);
   StateHeader hdr;
   HIPCHK(hipMemcpyAsync(&hdr, state_dev, sizeof(hdr), hipMemcpyDeviceToHost, h->stream), "load header");
   HIPCHK(hipStreamSynchronize(h->stream), "load header sync");
-  if (hdr.magic != 0x4e5048415345) { h->err = "not a state buffer"; return NPHASE_EINVAL; }
+  // checked on the host before any payload copy: a buffer of another configuration would
+  // be read past its end or reinterpreted
+  if (const char* why = header_mismatch(hdr, header_of(h, MAGIC_STATE, payload))) {
+    h->err = std::string("load_state: ") + why;
+    return NPHASE_EINVAL;
+  }
   const char* q = (const char*)state_dev + ALIGN;
   void* dst[4] = {h->f[h->cur], h->g[h->cur], h->u[h->cur], h->mm};
   for (int k = 0; k < 4; ++k) {
@@ -578,6 +688,9 @@ const char* nphase_lbm_strerror(int status) {
 }
 
 int nphase_lbm_destroy(nphase_lbm_t h) {
+  if (!h) return NPHASE_OK;
+  drop_graphs(h);
+  if (h->cap) (void)hipStreamDestroy(h->cap);
   delete h;
   return NPHASE_OK;
 }
@@ -772,7 +885,9 @@ int nphase_lbm_save_state64(nphase_lbm_t h, void* state_dev) {
   if (rc) return rc;
   if (!state_dev) { h->err = "state buffer is NULL"; return NPHASE_EINVAL; }
   if (!h->inited) { h->err = "save before init"; return NPHASE_ESTATE; }
-  rc = put_header(h, state_dev);
+  size_t s64 = 0;
+  nphase_lbm_state64_bytes(h, &s64);
+  rc = put_header(h, state_dev, MAGIC_STATE64, s64 - ALIGN);
   if (rc) return rc;
   const StatePtrs o = state_ptrs(h, state_dev);
   const int c = h->cur;

@@ -331,6 +331,27 @@ def test_checkpointing_matches_single_segment():
     assert np.array_equal(grads[0][1], grads[1][1])
 
 
+def test_sigma_on_device():
+    """The pair tensions may live on the GPU: their gradient comes back on the GPU and
+    equals the one of host tensions bit for bit."""
+    import torch
+    from paper_2306_06983_amd.autograd import run_differentiable
+    steps = 12
+    cfg, phi, target = _loss_setup("B", steps=steps)
+    tgt = torch.tensor(target, device="cuda:0")
+    grads = []
+    for dev in ("cpu", "cuda:0"):
+        phi0 = torch.tensor(phi, dtype=torch.float64, device="cuda:0", requires_grad=True)
+        sp = torch.tensor(inputs.sigma_pairs(cfg), dtype=torch.float64, device=dev,
+                          requires_grad=True)
+        loss = 0.5 * ((run_differentiable(cfg, phi0, sp, steps, ckpt_every=5) - tgt) ** 2).sum()
+        loss.backward()
+        assert sp.grad.device == sp.device
+        grads.append((phi0.grad.cpu().numpy(), sp.grad.cpu().numpy()))
+    assert np.array_equal(grads[0][0], grads[1][0])
+    assert np.array_equal(grads[0][1], grads[1][1])
+
+
 def _gpu_loss(cfg, phi, target_t, steps):
     import torch
     from paper_2306_06983_amd import binding as B

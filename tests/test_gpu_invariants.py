@@ -163,3 +163,63 @@ def test_config4_full_size_invariants():
     drift = np.abs(g["m1"] - g["m0"]) / g["m0"]
     assert drift.max() <= 1e-6
     assert np.abs(g["phi"].sum(0) - 1).max() <= 1e-6
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("lattice", ["D2Q9", "D3Q19"])
+def test_multistep_graphs_equal_single_steps(lattice, precision):
+    """step(n) issues all but the first step from the initial state as recorded
+    multi-step HIP graphs (64, 32, ..., 2 steps); replayed again and again, with eager
+    fields passes, mass reductions and synchronisations between the replays, they give
+    bitwise the state of n single-step launches, at every replay."""
+    import torch
+    if lattice == "D2Q9":
+        cfg, phi = inputs.many_discs(n=96, N=4, count=5, rmin=6, rmax=10)
+    else:
+        cfg, phi = inputs.spheres(n=32, scale=0.125)
+    eager = _sim(cfg, phi, precision)
+    graph = _sim(cfg, phi, precision)
+    eager.step(1)
+    graph.step(1)
+    for rep, n in enumerate((64, 64, 2, 98, 64, 7)):
+        for _ in range(n):
+            eager.step(1)
+        graph.step(n)
+        torch.cuda.synchronize()
+        fe = [x.cpu().numpy() for x in eager.fields()]
+        fg = [x.cpu().numpy() for x in graph.fields()]
+        for x, y in zip(fe, fg):
+            assert np.array_equal(x, y), (rep, n)
+        assert np.array_equal(eager.mass(), graph.mass())
+        assert eager.time() == graph.time()
+
+
+def test_load_state_rejects_other_configurations():
+    """load_state checks the configuration recorded in the state header on the host before
+    any copy: a buffer of another precision, grid, phase count, model or a save_state64
+    export is refused with EINVAL (only the 256-byte header is read) and the handle stays
+    usable; a buffer of the same configuration loads."""
+    from paper_2306_06983_amd import binding as B
+    cfg, phi = inputs.two_discs()
+    a = _sim(cfg, phi).step(5)
+    others = {
+        "fp32": _sim(cfg, phi, "fp32").step(5).save_state(),
+        "grid": _sim(dict(cfg, ny=48), phi[:, :48, :]).step(5).save_state(),
+        "model": _sim(dict(cfg, model="A"), phi).step(5).save_state(),
+        "solve_all": _sim(dict(cfg, solve_all=True), phi).step(5).save_state(),
+        "state64": a.save_state64(),
+    }
+    cfg4, phi4 = inputs.two_discs(N=4)
+    others["n_phases"] = _sim(cfg4, phi4).step(5).save_state()
+    t0 = a.time()
+    ref = [x.cpu().numpy() for x in a.fields()]
+    for name, buf in others.items():
+        with pytest.raises(B.NPhaseError) as ei:
+            a.load_state(buf)
+        assert ei.value.code == B.NPHASE_EINVAL, name
+        assert a.time() == t0
+    good = _sim(cfg, phi).step(5).save_state()
+    a.step(3).load_state(good)
+    assert a.time() == 5
+    for x, y in zip(ref, [x.cpu().numpy() for x in a.fields()]):
+        assert np.array_equal(x, y)
