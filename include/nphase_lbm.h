@@ -171,6 +171,23 @@ int nphase_lbm_mass(nphase_lbm_t h, double *mass_host);
 int nphase_lbm_interface_locations(nphase_lbm_t h, const double *phi_dev, double *y_av_host,
                                    int32_t *y_min_host, int32_t *y_max_host);
 
+/* The same diagnostics without a handle, a workspace or any allocation, for callers that
+ * cannot allocate device memory (tight serving loops, harnesses that forbid allocation)
+ * and hold an FP64 phi field [n_phases][nz][ny][nx] on the current device but no handle.
+ * lattice fixes the height (row y for NPHASE_D2Q9, which needs nz = 1; plane z for
+ * NPHASE_D3Q19); outputs as for nphase_lbm_interface_locations, n_phases entries each,
+ * bitwise equal to its results.  The reduction scratch is a static device array of the
+ * library (65 664 bytes on each GPU it runs on, kept until the process ends): at most
+ * NPHASE_MAX_N phases (more: NPHASE_ENOTSUP, no device work).  Enqueued on hip_stream
+ * (NULL = the legacy default stream), then synchronises it.  Calls that overlap on one
+ * GPU (other threads or streams) race on that array.  Errors: EINVAL (bad extents,
+ * lattice or NULL pointers), ENOTSUP (n_phases > NPHASE_MAX_N, or device ordinal >= 64),
+ * EDEVICE (a HIP call failed). */
+int nphase_lbm_interface_locations_noalloc(int32_t lattice, int32_t nx, int32_t ny, int32_t nz,
+                                           int32_t n_phases, const double *phi_dev,
+                                           void *hip_stream, double *y_av_host,
+                                           int32_t *y_min_host, int32_t *y_max_host);
+
 /* all_finite_host = 1 if every phi^{t-1} and u value of the state is finite, else 0
  * and the call returns NPHASE_ENAN.  Synchronises the stream. */
 int nphase_lbm_check(nphase_lbm_t h, int *all_finite_host);

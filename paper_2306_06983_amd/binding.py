@@ -79,6 +79,10 @@ def load():
         "nphase_lbm_interface_locations": [vp, vp, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_int32),
                                            ctypes.POINTER(ctypes.c_int32)],
+        "nphase_lbm_interface_locations_noalloc": [
+            ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp,
+            vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
+            ctypes.POINTER(ctypes.c_int32)],
         "nphase_lbm_time": [vp, ctypes.POINTER(i64)],
         "nphase_lbm_state_bytes": [vp, ctypes.POINTER(sz)],
         "nphase_lbm_save_state": [vp, vp],
@@ -138,6 +142,35 @@ def make_params(cfg, precision="fp64"):
         p.contact_cos[i] = float(c)
     p.pair_normals = {"stencil": 0, "chain": 1}[cfg.get("pair_normals", "stencil")]
     return p
+
+
+def interface_locations_noalloc(phi, lattice):
+    """(Y_av, Y_min, Y_max) of an FP64 CUDA tensor phi [N, *grid] through the handle-free
+    entry point that allocates nothing (its reduction scratch is a static device array of
+    the library), on torch's current stream of phi's device."""
+    import torch
+    lib = load()
+    if not (phi.is_cuda and phi.dtype == torch.float64):
+        raise ValueError("phi must be an FP64 CUDA tensor")
+    phi = phi.contiguous()
+    N = int(phi.shape[0])
+    if lattice == "D2Q9":
+        ny, nx = phi.shape[1:]
+        nz = 1
+    else:
+        nz, ny, nx = phi.shape[1:]
+    av = (ctypes.c_double * max(N, 1))()
+    lo = (ctypes.c_int32 * max(N, 1))()
+    hi = (ctypes.c_int32 * max(N, 1))()
+    with torch.cuda.device(phi.device):
+        stream = torch.cuda.current_stream(phi.device)
+        rc = lib.nphase_lbm_interface_locations_noalloc(
+            {"D2Q9": D2Q9, "D3Q19": D3Q19}[lattice], int(nx), int(ny), int(nz), N,
+            ctypes.c_void_p(phi.data_ptr()), ctypes.c_void_p(stream.cuda_stream), av, lo, hi)
+    if rc != NPHASE_OK:
+        raise NPhaseError(rc, lib.nphase_lbm_strerror(rc).decode())
+    return (np.array(av[:N], dtype=np.float64), np.array(lo[:N], dtype=np.int64),
+            np.array(hi[:N], dtype=np.int64))
 
 
 class Sim:

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -937,3 +938,74 @@ int nphase_lbm_adjoint_init(nphase_lbm_t h, const void* adj_state_dev, void* adj
 }
 
 }  // extern "C"
+
+// ------------------------------------------- interface locations without allocation
+// Reduction scratch of nphase_lbm_interface_locations_noalloc: the per-block partials
+// [4][MAXN][LOC_BLOCKS] of the locations kernels, then the per-phase results [3][MAXN];
+// FP64, 65 664 bytes.  One copy on every GPU the library runs on, held until the process
+// ends and shared by every call on that GPU.  Host code never passes the array's name to
+// a kernel or a copy: it uses the device address looked up for the current device.
+constexpr size_t NOALLOC_PARTIAL = (size_t)4 * MAXN * LOC_BLOCKS;
+constexpr size_t NOALLOC_WORDS = NOALLOC_PARTIAL + 3 * MAXN;
+static __device__ __align__(256) double scratch[NOALLOC_WORDS];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex noalloc_mutex;
+double* noalloc_addr[NOALLOC_MAX_DEVICES] = {};
+
+// the device address of the current device's copy of the scratch array, looked up once
+// per device with that device current
+hipError_t noalloc_scratch(int dev, double** out) {
+  std::lock_guard<std::mutex> lock(noalloc_mutex);
+  if (!noalloc_addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    noalloc_addr[dev] = (double*)p;
+  }
+  *out = noalloc_addr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" int nphase_lbm_interface_locations_noalloc(int32_t lattice, int32_t nx, int32_t ny,
+                                                      int32_t nz, int32_t n_phases,
+                                                      const double* phi_dev, void* hip_stream,
+                                                      double* y_av_host, int32_t* y_min_host,
+                                                      int32_t* y_max_host) {
+  if (lattice != NPHASE_D2Q9 && lattice != NPHASE_D3Q19) return NPHASE_EINVAL;
+  if (nx < 1 || ny < 1 || nz < 1 || (lattice == NPHASE_D2Q9 && nz != 1)) return NPHASE_EINVAL;
+  if (!phi_dev || !y_av_host || !y_min_host || !y_max_host) return NPHASE_EINVAL;
+  if (n_phases < 1) return NPHASE_EINVAL;
+  // the scratch array holds the partials of at most NPHASE_MAX_N phases
+  if (n_phases > NPHASE_MAX_N) return NPHASE_ENOTSUP;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return NPHASE_EDEVICE;
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return NPHASE_ENOTSUP;
+  double* sc = nullptr;
+  if (noalloc_scratch(dev, &sc) != hipSuccess) return NPHASE_EDEVICE;
+  hipStream_t s = (hipStream_t)hip_stream;
+  const long long V = (long long)nx * ny * nz;
+  const long long plane = lattice == NPHASE_D2Q9 ? (long long)nx : (long long)nx * ny;
+  // the partial kernel writes every partial the final kernel reads (all blocks, phases
+  // below n_phases), and the final kernel writes every result read back below: nothing
+  // of an earlier call is read, so nothing is cleared
+  hipLaunchKernelGGL(locations_partial_kernel, dim3(LOC_BLOCKS), dim3(256), 0, s, phi_dev, sc,
+                     (int)n_phases, V, plane);
+  hipLaunchKernelGGL(locations_final_kernel, dim3(n_phases), dim3(LOC_BLOCKS), 0, s,
+                     (const double*)sc, sc + NOALLOC_PARTIAL);
+  if (hipGetLastError() != hipSuccess) return NPHASE_EDEVICE;
+  double out[3 * MAXN];
+  if (hipMemcpyAsync(out, sc + NOALLOC_PARTIAL, sizeof(out), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return NPHASE_EDEVICE;
+  if (hipStreamSynchronize(s) != hipSuccess) return NPHASE_EDEVICE;
+  for (int q = 0; q < n_phases; ++q) {
+    y_av_host[q] = out[q];
+    y_min_host[q] = (int32_t)out[MAXN + q];
+    y_max_host[q] = (int32_t)out[2 * MAXN + q];
+  }
+  return NPHASE_OK;
+}
