@@ -42,6 +42,15 @@ CASES = {
     "d2q9_B_N5_60x44": (lambda: ragged_discs(60, 44, N=5, count=4), 100),
     "d2q9_B_N6_64x48": (lambda: ragged_discs(64, 48, N=6, count=5), 60),
     "d2q9_A1_N6_50x39": (lambda: ragged_discs(50, 39, N=6, model="A", count=5), 60),
+    # FP64 Model A with five evolved sets (N = 5 solving all) runs the 32 x 12 tile: a
+    # height that is not a multiple of 12; six evolved sets (N = 6 solving all)
+    "d2q9_A1_N5_solve_all_47x37": (lambda: ragged_discs(47, 37, N=5, model="A", solve_all=True,
+                                                         count=4), 60),
+    "d2q9_B_N6_solve_all_45x29": (lambda: ragged_discs(45, 29, N=6, solve_all=True, count=5,
+                                                                    rmin=3.0, rmax=4.0), 40),
+    "d2q9_A2_N6_solve_all_44x31": (lambda: ragged_discs(44, 31, N=6, model="A", model_a_n=2,
+                                                         solve_all=True, count=5, rmin=3.0,
+                                                         rmax=3.5), 40),
     "d2q9_B_tiny_3x16": (lambda: _tiny_band(3, 16), 80),
     "d2q9_B_tile_exact_64x32": (lambda: ragged_discs(64, 32, N=3, seed=11), 120),
     "d3q19_B_25x19x14": (lambda: ragged_spheres(25, 19, 14), 30),
@@ -49,6 +58,8 @@ CASES = {
     "d3q19_B_N3_solve_all_gravity": (lambda: ragged_spheres(20, 17, 15, N=3, solve_all=True,
                                                             gravity=(0, 0, -1e-5)), 25),
     "d3q19_B_tile_exact_16x16x8": (lambda: ragged_spheres(16, 16, 12, N=3, seed=5), 25),
+    # six evolved sets: the FP64 z-march takes its narrow 64 x 4 column tile
+    "d3q19_B_N6_solve_all_25x19x14": (lambda: ragged_spheres(25, 19, 14, N=6, solve_all=True), 12),
 }
 
 

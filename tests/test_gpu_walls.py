@@ -87,6 +87,13 @@ CASES = {
                                         cos_pN=[0.3, -0.2, 0.4, -0.5]), 60),
     "walls_A1_N6_52x29": (lambda: _discs(52, 29, N=6, model="A", count=5, rmin=3.0, rmax=3.5,
                                          cos_pN=[0.2, -0.4, 0.5, -0.1, 0.3]), 50),
+    # FP64 Model A solving all five sets (32 x 12 tile), height not a multiple of 12
+    "walls_A1_N5_solve_all_40x27": (lambda: _discs(40, 27, N=5, model="A", solve_all=True,
+                                                   count=4, rmin=3.0, rmax=4.5,
+                                                   cos_pN=[0.2, -0.3, 0.4, -0.1]), 50),
+    "walls_B_N6_solve_all_44x29": (lambda: _discs(44, 29, N=6, solve_all=True, count=5,
+                                                  rmin=3.0, rmax=3.5,
+                                                  cos_pN=[0.1, -0.2, 0.3, -0.4, 0.2]), 40),
     "walls3d_B_N4_21x17x19": (lambda: _spheres(21, 17, 19, cos_pN=[0.4, -0.3, 0.2]), 30),
     "walls3d_A2_N3_solve_all_gravity_18x14x37": (
         lambda: _spheres(18, 14, 37, N=3, model="A", model_a_n=2, solve_all=True,
