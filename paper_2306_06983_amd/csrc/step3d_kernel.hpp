@@ -419,7 +419,7 @@ __global__ void __launch_bounds__((Z3Tile<T, (SA ? N : N - 1)>::NT), 2)
           for (int q = p + 1; q < N; ++q, ++k) {
             T v;
             if constexpr (PF_LDS) v = s_pf[k][ring_of(zz, 3)][rr];
-            else v = pair_fraction(ph[p], ph[q]);
+            else v = pair_fraction_fast(ph[p], ph[q]);
 #pragma unroll
             for (int d = 0; d < D; ++d) {
               if (L::c(i, d) == 1) H[k][d] += wg * v;

@@ -300,6 +300,27 @@ __device__ __forceinline__ T pair_fraction(T pp, T pq) {
   return (s > T(PAIR_EPS)) ? pp / s : T(0.5);
 }
 
+// The same fraction with the quotient from the hardware reciprocal estimate refined by two
+// Newton-Raphson steps and one residual correction (FP64; within an ulp of pp / s), for
+// the stencils that recompute the fractions of every neighbour
+template <typename T>
+__device__ __forceinline__ T pair_fraction_fast(T pp, T pq) {
+  if constexpr (sizeof(T) == 8) {
+    // where the guard applies the quotient may be inf or NaN: it is not selected
+    const double s = pp + pq;
+    double r = __builtin_amdgcn_rcp(s);
+    double e = __builtin_fma(-s, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-s, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    double q = pp * r;
+    q = __builtin_fma(r, __builtin_fma(-s, q, pp), q);
+    return s > PAIR_EPS ? q : 0.5;
+  } else {
+    return pair_fraction(pp, pq);
+  }
+}
+
 template <typename T, int LAT, int N, bool SA, int MODEL, int MODE>
 __global__ void __launch_bounds__((StepTile<T, LAT, N, SA, MODEL>::NT),
                                   (StepTile<T, LAT, N, SA, MODEL>::MINW))
