@@ -128,7 +128,10 @@ int nphase_lbm_workspace_bytes(const nphase_lbm_params *params, size_t *bytes_ho
 
 /* Validate and copy the parameters, carve the caller's workspace and bind the stream.
  * Errors: EINVAL (bad parameters, NULL pointers, misaligned workspace), ENOMEM
- * (ws_bytes too small), ENOTSUP (N outside 2..6).  No device work is done. */
+ * (ws_bytes too small), ENOTSUP (N outside 2..6).  No device work is done.  The D3Q19
+ * passes split z into runs whose length is chosen for the device's compute-unit count
+ * (read here); the environment variable NPHASE_CU_COUNT, if set to a positive integer,
+ * replaces that count (results do not depend on it). */
 int nphase_lbm_create(const nphase_lbm_params *params, void *workspace_dev, size_t ws_bytes,
                       void *hip_stream, nphase_lbm_t *out_host);
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -40,6 +41,7 @@ struct nphase_lbm_s {
   int64_t t = 0;
   double rho_bar = 0.0;
   int ntx = 0, nty = 0, ntz = 0, ntiles = 0;
+  int cus = 256;   // compute units of the device
   bool inited = false;
   bool failed = false;
   std::string err;
@@ -201,6 +203,8 @@ void fill_args(nphase_lbm_t h, StepArgs<T>* out) {
     a.nty = h->nty;
     a.ntz = h->ntz;
     a.ntiles = h->ntiles;
+    a.cus = h->cus;
+    a.zr = Z3_ZR;
     a.V = h->V;
     a.model_a_n = p.model_a_n;
     for (int i = 0; i < h->N; ++i) {
@@ -358,6 +362,15 @@ int nphase_lbm_create(const nphase_lbm_params* params, void* workspace_dev, size
   h->V = (long long)params->nx * params->ny * params->nz;
   h->stream = (hipStream_t)hip_stream;
   if (hipGetDevice(&h->device) != hipSuccess) h->device = 0;
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess && ncu > 0)
+    h->cus = ncu;
+  // the D3Q19 z-run length is chosen for this many compute units; NPHASE_CU_COUNT sets
+  // another count (tests use it to run long z-runs on small grids)
+  if (const char* env = std::getenv("NPHASE_CU_COUNT")) {
+    const int v = std::atoi(env);
+    if (v > 0) h->cus = v;
+  }
   h->ws = (char*)workspace_dev;
   h->ws_bytes = ws_bytes;
   char* q = h->ws;

@@ -17,7 +17,7 @@
 //
 // nphase_step3d_kernel: a workgroup owns a TX x TY column tile (one thread per column:
 // 64 x 8 in FP64 and 32 x 16 in FP32, 512 threads, where the LDS rings of the evolved sets
-// fit one CU; else 64 x 4 and 32 x 8, 256 threads) and a run of ZR planes in z.  It marches
+// fit one CU; else 64 x 4 and 32 x 8, 256 threads) and a run of planes in z.  It marches
 // through the run with a three-stage pipeline, one plane per stage and iteration:
 //   S1 plane z+2   phi (and Model B pair fractions) on the tile plus a 2-node ring in x,y,
 //                  from the moments, into a ring of LDS planes;
@@ -61,7 +61,19 @@ struct Z3Tile {
   static constexpr int NT = TX * TY;
   static constexpr int BUDGET = TALL ? 163840 : 81920;   // LDS of one workgroup
 };
-constexpr int Z3_ZR = 32;   // planes per workgroup run
+// Planes per workgroup run of both z-marching passes: the longest power of two up to 128
+// that still gives every compute unit as many workgroups as its LDS holds (`per_cu`), so
+// that large grids recompute few pipeline-fill planes (4 per run here, the 2 halo planes of
+// the moments pass) and small ones still fill the device.  Measured on 256^3 N = 4: FP64
+// runs of 128 planes 7 % faster than 32, FP32 runs of 64 5 % faster (its moments pass fits
+// two workgroups per CU).
+inline int z_run_length(int ncols, int nz, int cus, int per_cu) {
+  const long long want = (long long)cus * per_cu;
+  int zr = 128;
+  while (zr > 1 && (long long)ncols * ((nz + zr - 1) / zr) < want) zr >>= 1;
+  return zr;
+}
+constexpr int Z3_ZR = 32;   // planes per run assumed by the host's tile count (informational)
 
 // Moments of one node, layout mo[NM][V]: [p] phi_p, [NS + p D + d] j_{p,d}, and for FP32
 // [NS + NS D + p] the two-sum residual (phi^{t-1} + sum f~) - phi of the rounded phi.
@@ -70,12 +82,15 @@ constexpr int n_moments() {
   return NS * 4 + (sizeof(T) == 4 ? NS : 0);
 }
 
-// Column tile and run of the moments pass: 64 x 8 columns (512 threads), 32 planes.  It
-// marches in z per evolved set with a 3-plane LDS ring of the moment fields (tile + 1-node
-// ring in x,y: 111 KB in FP64, one workgroup per CU; 55 KB in FP32, two), so every stored
-// value is read from memory about 1.29 times (the x,y halo) instead of once per neighbour
-// that pulls from it.  (64 x 4 measured 5 % slower on this pass in FP64, equal in FP32.)
-constexpr int M3_TX = 64, M3_TY = 8, M3_ZR = 32, M3_NT = M3_TX * M3_TY;
+// Column tile of the moments pass: 64 x 8 columns (512 threads), a run of planes in z (see
+// z_run_length).  It marches in z per evolved set with a 3-plane LDS ring of the moment
+// fields (tile + 1-node ring in x,y: 111 KB in FP64, one workgroup per CU; 55 KB in FP32,
+// two), so every stored value is read from memory about 1.29 times (the x,y halo) instead
+// of once per neighbour that pulls from it.  (64 x 4 measured 5 % slower on this pass in
+// FP64, equal in FP32.)
+constexpr int M3_TX = 64, M3_TY = 8, M3_NT = M3_TX * M3_TY;
+template <typename T>
+constexpr int m3_per_cu() { return sizeof(T) == 8 ? 1 : 2; }   // workgroups per CU by LDS
 
 template <typename T, int NS>
 __global__ void __launch_bounds__(M3_NT, sizeof(T) == 4 ? 4 : 2) nphase_moments3d_kernel(const StepArgs<T> a) {
@@ -83,7 +98,8 @@ __global__ void __launch_bounds__(M3_NT, sizeof(T) == 4 ? 4 : 2) nphase_moments3
   constexpr int D = 3, Q = 19, NMR = MR<T>::N;
   constexpr int NF = 7;   // phi, A, D: the fields pulled from neighbours
   constexpr bool DEV = sizeof(T) == 4;
-  constexpr int TX = M3_TX, TY = M3_TY, ZR = M3_ZR;
+  constexpr int TX = M3_TX, TY = M3_TY;
+  const int ZR = a.zr;
   constexpr int RX = TX + 2, RY = TY + 2, RP = RX * RY;
   __shared__ T s_mr[3][NF][RP];
 
@@ -250,7 +266,8 @@ __global__ void __launch_bounds__((Z3Tile<T, (SA ? N : N - 1)>::NT), 2)
   constexpr int NP = N * (N - 1) / 2;
   constexpr bool DEV = sizeof(T) == 4;
   using ZT = Z3Tile<T, (SA ? N : N - 1)>;
-  constexpr int TX = ZT::TX, TY = ZT::TY, ZR = Z3_ZR;
+  constexpr int TX = ZT::TX, TY = ZT::TY;
+  const int ZR = a.zr;
   constexpr int RX = TX + 4, RY = TY + 4, RP = RX * RY;   // region plane (2-node ring)
   constexpr int IX = TX + 2, IY = TY + 2, IP = IX * IY;   // inner plane (1-node ring)
   constexpr int PHR = DEV ? 4 : 3;                        // phi ring depth

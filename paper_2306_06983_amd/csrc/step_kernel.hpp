@@ -75,6 +75,8 @@ struct StepArgs {
   double* p_out;     // fields mode: [V]
   int nx, ny, nz;
   int ntx, nty, ntz, ntiles;
+  int zr;            // D3Q19: planes per workgroup run of the z-marching passes
+  int cus;           // compute units of the device (the z-run length is chosen for them)
   long long V;
   int model_a_n;
   T rho[MAXN];

@@ -223,3 +223,27 @@ def test_load_state_rejects_other_configurations():
     assert a.time() == 5
     for x, y in zip(ref, [x.cpu().numpy() for x in a.fields()]):
         assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("walls", [False, True])
+def test_z_run_length_does_not_change_results(precision, walls, monkeypatch):
+    """The D3Q19 passes split z into runs whose length follows the device's compute-unit
+    count; a handle created for 4 compute units (runs of 16 and 32 planes on this grid)
+    and one for the device's own count (runs of one plane) give bitwise the same state
+    (with walls too: the runs that start or end at a wall), and both match the oracle."""
+    import torch
+    from _helpers import ragged_spheres
+    cfg, phi = ragged_spheres(25, 19, 37, N=4)
+    if walls:
+        cfg = dict(cfg, walls=True, contact_cos=[0.3, -0.2, 0.4])
+    monkeypatch.setenv("NPHASE_CU_COUNT", "4")
+    long_runs = run_gpu(cfg, phi, 12, precision)
+    monkeypatch.delenv("NPHASE_CU_COUNT")
+    short_runs = run_gpu(cfg, phi, 12, precision)
+    for k in ("phi", "u", "P"):
+        assert np.array_equal(long_runs[k], short_runs[k]), k
+    if precision == "fp64":
+        o = run_oracle(cfg, phi, 12)
+        assert max(errors(long_runs, o)) <= 1e-12
+    torch.cuda.synchronize()
