@@ -270,16 +270,21 @@ __global__ void __launch_bounds__((Z3Tile<T, (SA ? N : N - 1)>::NT), 2)
   const int ZR = a.zr;
   constexpr int RX = TX + 4, RY = TY + 4, RP = RX * RY;   // region plane (2-node ring)
   constexpr int IX = TX + 2, IY = TY + 2, IP = IX * IY;   // inner plane (1-node ring)
-  constexpr int PHR = DEV ? 4 : 3;                        // phi ring depth
   constexpr int WR = 3;                                   // tensor ring depth
   constexpr T CS2 = T(1) / T(3);
   // LDS budget: 2 waves per SIMD per CU in both precisions (two 256-thread workgroups or
-  // one 512-thread one); the Model B pair fractions are staged when they fit, else
-  // recomputed at every stencil point (FP64: two waves per SIMD with the recomputation beat
-  // one wave with staged fractions)
+  // one 512-thread one); the Model B pair fractions are staged when they fit with a 3-plane
+  // phi ring, else recomputed at every stencil point (FP64: two waves per SIMD with the
+  // recomputation beat one wave with staged fractions)
   constexpr int BUDGET = ZT::BUDGET;
-  constexpr int BASE = sizeof(T) * (NS * PHR * RP + 3 * WR * IP);
-  constexpr bool PF_LDS = (MODEL == MODEL_B) && BASE + (int)sizeof(T) * NP * 3 * RP <= BUDGET;
+  constexpr int PFB = (int)sizeof(T) * NP * 3 * RP;       // staged pair fractions
+  // phi ring depth: FP32 keeps four planes; FP64 decides the staging with three and takes
+  // a fourth plane where it still fits (it spares the barrier before each S1, which would
+  // otherwise overwrite the plane the previous S3 read)
+  constexpr int BASE_PF = sizeof(T) * (NS * (DEV ? 4 : 3) * RP + 3 * WR * IP);
+  constexpr bool PF_LDS = (MODEL == MODEL_B) && BASE_PF + PFB <= BUDGET;
+  constexpr bool PHR4 = DEV || (sizeof(T) * (NS * 4 * RP + 3 * WR * IP) + (PF_LDS ? PFB : 0) <= BUDGET);
+  constexpr int PHR = PHR4 ? 4 : 3;
 
   __shared__ T s_phi[NS][PHR][RP];
   __shared__ T s_pf[PF_LDS ? NP : 1][PF_LDS ? 3 : 1][PF_LDS ? RP : 1];
