@@ -150,7 +150,9 @@ int nphase_lbm_init(nphase_lbm_t h, const double *phi0_dev);
  * graphs of 64, 32, ..., 2 steps (binary decomposition of the count, at most one single
  * step left over), recorded once per handle on a private stream (default priority) and
  * launched on the handle's stream; init and load_state discard them.  The graphs hold
- * kernel nodes only.  Results are bitwise those of single steps.
+ * kernel nodes only.  Results are bitwise those of single steps.  While the handle's
+ * stream is being captured by the caller, every step is a plain launch (so the caller's
+ * graph records the kernels themselves).
  * Asynchronous on the stream. */
 int nphase_lbm_step(nphase_lbm_t h, int64_t nsteps);
 

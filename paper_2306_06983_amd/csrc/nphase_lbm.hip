@@ -439,8 +439,11 @@ int nphase_lbm_step(nphase_lbm_t h, int64_t nsteps) {
     left -= 1;
   }
   // the rest as multi-step graphs of 64, 32, ..., 2 steps (binary decomposition), then
-  // at most one single step
-  for (int k = 5; k >= 0; --k) {
+  // at most one single step; a caller that is capturing the stream itself gets plain
+  // launches (no nested capture, no graph launched into its capture)
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(h->stream, &cs) != hipSuccess) cs = hipStreamCaptureStatusNone;
+  for (int k = cs == hipStreamCaptureStatusNone ? 5 : -1; k >= 0; --k) {
     const int64_t n = 2 << k;
     while (left >= n) {
       hipGraphExec_t g = nullptr;
@@ -450,10 +453,11 @@ int nphase_lbm_step(nphase_lbm_t h, int64_t nsteps) {
       left -= n;
     }
   }
-  if (left > 0) {
+  while (left > 0) {
     HIPCHK(launch(h, MODE_STEP, h->cur), "step kernel");
     h->cur ^= 1;
     h->t += 1;
+    left -= 1;
   }
   return NPHASE_OK;
 }

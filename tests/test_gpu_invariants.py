@@ -247,3 +247,37 @@ def test_z_run_length_does_not_change_results(precision, walls, monkeypatch):
         o = run_oracle(cfg, phi, 12)
         assert max(errors(long_runs, o)) <= 1e-12
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("lattice", ["D2Q9", "D3Q19"])
+def test_step_captured_by_the_caller(lattice):
+    """A caller may capture nphase_lbm_step into its own graph on the handle's stream: the
+    step then records plain kernel launches (no nested capture).  The captured six steps,
+    replayed again and again with eager work and synchronisations between the replays, give
+    bitwise the state of a handle stepped eagerly, at every replay."""
+    import torch
+    from paper_2306_06983_amd import binding as B
+    if lattice == "D2Q9":
+        cfg, phi = inputs.many_discs(n=96, N=4, count=5, rmin=6, rmax=10)
+    else:
+        cfg, phi = inputs.spheres(n=32, scale=0.125)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        cap = B.Sim(cfg, "fp64").init(phi)
+    ref = _sim(cfg, phi)
+    cap.step(1)          # the step from the initial state stays outside the graph
+    ref.step(1)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        cap.step(6)      # recorded, not run
+    for rep in range(4):
+        g.replay()
+        s.synchronize()
+        ref.step(6)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            fc = [x.cpu().numpy() for x in cap.fields()]
+        fr = [x.cpu().numpy() for x in ref.fields()]
+        for x, y in zip(fc, fr):
+            assert np.array_equal(x, y), rep
