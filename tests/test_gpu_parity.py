@@ -3,8 +3,9 @@ element, plus the invariants of the method on the GPU.
 
 Bars:
   FP64: max |dphi| <= 1e-12 and max |du| / max |u|, max |dP| / max |P| <= 1e-12.
-  FP32 (deviation storage): max |dphi| <= max(2e-5, 3x the oracle's own change under a
-  relative 6e-8 perturbation of phi0), per-phase relative mass drift <= 1e-6.
+  FP32 (deviation storage): max |dphi| <= 2e-5 (for the one named ill-conditioned case,
+  whose oracle moves by 8e-3 under a relative 6e-8 perturbation of phi0: 3x that spread),
+  per-phase relative mass drift <= 1e-6.
   FP64 mass conservation: <= 1e-12 relative (summation round-off over the run).
 The touching-disc workload (64^2, N = 3) amplifies round-off: in the oracle itself a
 one-rounding perturbation of phi0 (relative 2.2e-16) grows to 4e-7 .. 2e-5 by step 2000,
@@ -99,17 +100,28 @@ def _fp32_envelope(cfg, phi, steps, o):
     return float(np.abs(run_oracle(cfg, p, steps)["phi"] - o["phi"]).max())
 
 
+# Cases whose phase field the oracle itself cannot fix to 2e-5 at their horizon: the 3 x 16
+# band is so thin that its symmetry rows have a flat gradient where 4 phi (1 - phi)/eps is
+# not small, so the interface normal there is set by rounding; a relative 6e-8 perturbation
+# of phi0 moves the oracle by 8e-3 after 80 steps.  Only these are held to 3x that spread.
+ILL_CONDITIONED = {"d2q9_B_tiny_3x16"}
+
+
 def test_fp32_deviation_parity(case):
     name, cfg, phi, steps, o = case
     g = run_gpu(cfg, phi, steps, "fp32")
     dphi, du, dP = errors(g, o)
     present = np.abs(o["m0"]) > 0
     drift = np.abs(g["m1"] - o["m0"])[present] / np.abs(o["m0"])[present]
-    env = _fp32_envelope(cfg, phi, steps, o)
-    print(f"  fp32 dphi={dphi:.2e} du={du:.2e} dP={dP:.2e} drift={drift.max():.2e} "
-          f"envelope={env:.2e}")
+    print(f"  fp32 dphi={dphi:.2e} du={du:.2e} dP={dP:.2e} drift={drift.max():.2e}")
     assert g["finite"]
-    assert dphi <= max(FP32_PHI_TOL, 3 * env)
+    if name in ILL_CONDITIONED:
+        env = _fp32_envelope(cfg, phi, steps, o)
+        print(f"  ill-conditioned case: oracle spread under a 6e-8 perturbation {env:.2e}")
+        assert dphi > FP32_PHI_TOL   # keep the list honest: a case that meets the bar leaves it
+        assert dphi <= 3 * env
+    else:
+        assert dphi <= FP32_PHI_TOL
     assert drift.max() <= FP32_MASS_TOL
     # an absent phase stays exactly absent in FP32 too
     for k in np.nonzero(~present)[0]:
@@ -146,8 +158,7 @@ def test_two_discs_full_length():
     assert np.abs(g["phi"].sum(0) - 1).max() <= 1e-14
     g32 = run_gpu(cfg, phi, 2000, "fp32")
     e32 = errors(g32, o)
-    env = _fp32_envelope(cfg, phi, 2000, o)
-    print(f"  2000 steps fp32 dphi={e32[0]:.2e} envelope={env:.2e}")
-    # the envelope perturbs phi0 once; FP32 storage rounds at every one of the 2000 steps
-    assert e32[0] <= max(FP32_PHI_TOL, 10 * env)
+    print(f"  2000 steps fp32 dphi={e32[0]:.2e}")
+    # the fixed bar holds here at the full horizon (observed 3e-6)
+    assert e32[0] <= FP32_PHI_TOL
     assert np.all(np.abs(g32["m1"] - g["m0"]) <= FP32_MASS_TOL * g["m0"])
