@@ -65,7 +65,7 @@ enum { NPHASE_MODEL_A = 0, NPHASE_MODEL_B = 1 };
  *   arithmetic; the initial equilibrium set-up and the per-phase mass reductions are FP64. */
 enum { NPHASE_FP64 = 0, NPHASE_FP32 = 1 };
 
-#define NPHASE_MAX_N 8 /* size of the parameter arrays; the library evolves N in [2, 6] */
+#define NPHASE_MAX_N 8 /* size of the parameter arrays; the library evolves N in [2, 8] */
 
 typedef struct nphase_lbm_s *nphase_lbm_t;
 
@@ -127,8 +127,8 @@ typedef struct {
 int nphase_lbm_workspace_bytes(const nphase_lbm_params *params, size_t *bytes_host);
 
 /* Validate and copy the parameters, carve the caller's workspace and bind the stream.
- * Errors: EINVAL (bad parameters, NULL pointers, misaligned workspace), ENOMEM
- * (ws_bytes too small), ENOTSUP (N outside 2..6).  No device work is done.  The D3Q19
+ * Errors: EINVAL (bad parameters, N outside [2, NPHASE_MAX_N] included, NULL pointers,
+ * misaligned workspace), ENOMEM (ws_bytes too small).  No device work is done.  The D3Q19
  * passes split z into runs whose length is chosen for the device's compute-unit count
  * (read here); the environment variable NPHASE_CU_COUNT, if set to a positive integer,
  * replaces that count (results do not depend on it). */

@@ -2,8 +2,8 @@
 
     python -m paper_2306_06983_amd.build [--only-n N] [-j JOBS]
 
-Compiles the four kernel translation units (FP64/FP32 x D2Q9/D3Q19) and the host C-ABI
-unit in parallel, then links the shared library next to this file.  `--only-n` limits
+Compiles the kernel translation units (FP64/FP32 x D2Q9/D3Q19, the D3Q19 ones split by
+phase count; the two adjoint units) and the host C-ABI unit in parallel, then links the shared library next to this file.  `--only-n` limits
 the instantiated phase counts to one value (faster development builds)."""
 import argparse
 import concurrent.futures as cf
@@ -15,9 +15,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnphase_lbm.so")
-SOURCES = ["nphase_lbm.hip", "kernels_f64_d2q9.hip", "kernels_f32_d2q9.hip",
-           "adjoint_d2q9.hip", "adjoint_d3q19.hip",
-           "kernels_f64_d3q19.hip", "kernels_f32_d3q19.hip"]
+# the D3Q19 step units are split by phase count: the longest unit sets the build time
+SOURCES = ["kernels_f64_d3q19_n7to8.hip", "kernels_f64_d3q19_n5to6.hip",
+           "kernels_f32_d3q19_n6to8.hip", "kernels_f64_d3q19_n2to4.hip",
+           "kernels_f32_d3q19_n2to5.hip", "kernels_f64_d2q9.hip", "kernels_f32_d2q9.hip",
+           "adjoint_d3q19.hip", "adjoint_d2q9.hip", "nphase_lbm.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # no packed-FP32 instructions in any HIP code

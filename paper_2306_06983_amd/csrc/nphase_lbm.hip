@@ -136,7 +136,7 @@ int validate(const nphase_lbm_params* p, std::string* why) {
         return bad("contact_cos must lie in [-1, 1]");
   }
   if (N < NMIN || N > NMAX) {
-    if (why) *why = "n_phases outside the instantiated range [2, 6]";
+    if (why) *why = "n_phases outside the instantiated range [2, 8]";
     return NPHASE_ENOTSUP;
   }
   return NPHASE_OK;

@@ -157,7 +157,11 @@ struct StepTile {
   static constexpr bool T12 = LAT == LAT_D2Q9 && sizeof(T) == 8 && MODEL == MODEL_A && !TALL &&
                               step2d_lds_bytes<T, N, SA, MODEL, 8>() > (size_t)163840 / 2 &&
                               step2d_lds_bytes<T, N, SA, MODEL, 12>() <= (size_t)163840;
-  static constexpr int TY = SQ32 ? 32 : (TALL ? 16 : (T12 ? 12 : TileShape<LAT>::TY));
+  // FP64 with seven or eight evolved sets (N = 8, or N = 7 solving all): the staged moment
+  // form of 32 x 8 exceeds a CU's LDS (173 KB at seven sets); 32 x 4 (128 threads) fits
+  static constexpr bool T4 = LAT == LAT_D2Q9 && sizeof(T) == 8 && !TALL && !T12 &&
+                             step2d_lds_bytes<T, N, SA, MODEL, 8>() > (size_t)163840;
+  static constexpr int TY = SQ32 ? 32 : (TALL ? 16 : (T12 ? 12 : (T4 ? 4 : TileShape<LAT>::TY)));
   static constexpr int TZ = TileShape<LAT>::TZ;
   static constexpr int NT = TX * TY * TZ;
 };

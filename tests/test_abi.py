@@ -109,12 +109,22 @@ def test_invalid_parameters_rejected(lib, mutate, code):
     assert rc2 == code and not h.value
 
 
-def test_unsupported_phase_count(lib):
-    N = 7
-    cfg = inputs.base_cfg("D2Q9", 16, 16, 1, N, inputs.uniform_sigma(N, 0.01), [1.0] * N,
-                          [0.8] * N)
-    rc, _ = _ws(lib, B.make_params(cfg))
-    assert rc == B.NPHASE_ENOTSUP
+@pytest.mark.parametrize("lattice,nz", [("D2Q9", 1), ("D3Q19", 8)])
+def test_phase_count_range(lib, lattice, nz):
+    """Every N in [2, NPHASE_MAX_N] is instantiated (both lattices): the workspace query
+    succeeds; N = 1 and N = NPHASE_MAX_N + 1 are invalid parameters."""
+    for N in range(2, 9):
+        cfg = inputs.base_cfg(lattice, 16, 16, nz, N, inputs.uniform_sigma(N, 0.01),
+                              [1.0] * N, [0.8] * N)
+        for sa in (False, True):
+            rc, ws = _ws(lib, B.make_params(dict(cfg, solve_all=sa)))
+            assert rc == B.NPHASE_OK and ws > 0, (N, sa)
+    cfg = inputs.base_cfg(lattice, 16, 16, nz, 8, inputs.uniform_sigma(8, 0.01), [1.0] * 8,
+                          [0.8] * 8)
+    for bad_n in (1, 9):
+        p = B.make_params(cfg)
+        p.n_phases = bad_n
+        assert _ws(lib, p)[0] == B.NPHASE_EINVAL
 
 
 def test_walls_need_two_planes(lib):

@@ -170,6 +170,35 @@ def test_adjoint_step_dot_product_walls(lattice, shape, model, solve_all, comp):
     assert abs(adj - fd) <= 1e-6 * max(abs(fd), 1e-12)
 
 
+@pytest.mark.parametrize("comp", ["f", "g", "pm"])
+@pytest.mark.parametrize("lattice,shape,N,model,solve_all,walls", [
+    ("D2Q9", (17, 20), 2, "B", False, False), ("D2Q9", (17, 20), 4, "A", True, False),
+    ("D2Q9", (17, 20), 5, "BC", False, True), ("D2Q9", (17, 20), 6, "B", True, False),
+    ("D2Q9", (17, 20), 7, "A", False, True), ("D2Q9", (17, 20), 8, "B", True, False),
+    ("D2Q9", (13, 18), 8, "BC", False, True),
+    ("D3Q19", (7, 8, 9), 2, "A", True, False), ("D3Q19", (7, 8, 9), 5, "B", False, True),
+    ("D3Q19", (7, 8, 9), 6, "BC", True, False), ("D3Q19", (7, 8, 9), 7, "B", True, False),
+    ("D3Q19", (7, 8, 9), 8, "A", False, True)])
+def test_adjoint_step_dot_product_phase_counts(lattice, shape, N, model, solve_all, walls,
+                                               comp):
+    """The adjoint step of every instantiated phase count (2 .. 8), each with a different
+    model / solve-all / walls combination, on an all-phases-present mixture."""
+    cfg, phi = _mixture(lattice, shape, N, seed=N + len(comp), model=model[0],
+                        solve_all=solve_all)
+    if walls:
+        rng = np.random.default_rng(N)
+        cfg = dict(cfg, walls=True,
+                   contact_cos=[float(c) for c in rng.uniform(-0.5, 0.5, N - 1)])
+    if model == "A":
+        cfg = dict(cfg, model_a_n=2)
+    if model == "BC":
+        cfg = dict(cfg, pair_normals="chain")
+    fd, adj = _dot_test(cfg, phi, comp)
+    print(f"  {lattice} N={N} {model} sa={solve_all} walls={walls} {comp}: "
+          f"fd={fd:.10e} adj={adj:.10e}")
+    assert abs(adj - fd) <= 1e-6 * max(abs(fd), 1e-12)
+
+
 def _loss_setup(model="B", n=48, steps=60, gravity=(0.0, 0.0, 0.0)):
     cfg, phi = inputs.many_discs(n=n, N=3, count=3, rmin=6, rmax=9, model=model, seed=12)
     cfg = dict(cfg, gravity=list(gravity))

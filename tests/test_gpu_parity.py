@@ -33,6 +33,12 @@ def _tiny_band(nx, ny, N=3):
     return cfg, phi
 
 
+def _chain(c):
+    """Model B with the chain-rule pair normals."""
+    cfg, phi = c
+    return dict(cfg, pair_normals="chain"), phi
+
+
 CASES = {
     "d2q9_B_gravity_50x37": (lambda: ragged_discs(50, 37, gravity=(0, -1e-5, 0)), 200),
     "d2q9_A1_50x37": (lambda: ragged_discs(50, 37, model="A"), 200),
@@ -61,6 +67,21 @@ CASES = {
     "d3q19_B_tile_exact_16x16x8": (lambda: ragged_spheres(16, 16, 12, N=3, seed=5), 25),
     # six evolved sets: the FP64 z-march takes its narrow 64 x 4 column tile
     "d3q19_B_N6_solve_all_25x19x14": (lambda: ragged_spheres(25, 19, 14, N=6, solve_all=True), 12),
+    # seven and eight phases; FP64 with seven or eight evolved sets runs the 32 x 4 D2Q9
+    # tile (heights 33 and 39: ragged against 4)
+    "d2q9_B_N7_50x40": (lambda: ragged_discs(50, 40, N=7, count=6, rmin=3.0, rmax=4.5), 40),
+    "d2q9_A1_N7_solve_all_50x33": (lambda: ragged_discs(50, 33, N=7, model="A", solve_all=True,
+                                                         count=6, rmin=3.0, rmax=3.5), 40),
+    "d2q9_B_N8_55x39": (lambda: ragged_discs(55, 39, N=8, count=7, rmin=3.0, rmax=3.5), 40),
+    "d2q9_A2_N8_solve_all_55x39": (lambda: ragged_discs(55, 39, N=8, model="A", model_a_n=2,
+                                                         solve_all=True, count=7, rmin=3.0,
+                                                         rmax=3.5), 30),
+    "d2q9_chain_N8_solve_all_60x41": (lambda: _chain(ragged_discs(60, 41, N=8, solve_all=True,
+                                                                  count=7, rmin=3.0,
+                                                                  rmax=3.5)), 30),
+    "d3q19_B_N7_25x19x14": (lambda: ragged_spheres(25, 19, 14, N=7), 12),
+    "d3q19_A1_N8_solve_all_25x19x14": (lambda: ragged_spheres(25, 19, 14, N=8, model="A",
+                                                              solve_all=True), 10),
 }
 
 

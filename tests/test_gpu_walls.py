@@ -94,6 +94,16 @@ CASES = {
     "walls_B_N6_solve_all_44x29": (lambda: _discs(44, 29, N=6, solve_all=True, count=5,
                                                   rmin=3.0, rmax=3.5,
                                                   cos_pN=[0.1, -0.2, 0.3, -0.4, 0.2]), 40),
+    # seven and eight phases (FP64 with seven or eight evolved sets: the 32 x 4 tile)
+    "walls_B_N7_55x35": (lambda: _discs(55, 35, N=7, count=6, rmin=3.0, rmax=3.5,
+                                        cos_pN=[0.3, -0.2, 0.4, -0.5, 0.1, -0.3]), 40),
+    "walls_A1_N8_solve_all_60x41": (lambda: _discs(60, 41, N=8, model="A", solve_all=True,
+                                                   count=7, rmin=3.0, rmax=3.5,
+                                                   cos_pN=[0.2, -0.4, 0.5, -0.1, 0.3, -0.2,
+                                                           0.1]), 30),
+    "walls3d_B_N8_25x19x14": (lambda: _spheres(25, 19, 14, N=8,
+                                               cos_pN=[0.4, -0.3, 0.2, -0.1, 0.3, -0.2, 0.1]),
+                              10),
     "walls3d_B_N4_21x17x19": (lambda: _spheres(21, 17, 19, cos_pN=[0.4, -0.3, 0.2]), 30),
     "walls3d_A2_N3_solve_all_gravity_18x14x37": (
         lambda: _spheres(18, 14, 37, N=3, model="A", model_a_n=2, solve_all=True,
