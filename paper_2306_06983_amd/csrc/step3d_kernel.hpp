@@ -43,16 +43,18 @@
 
 namespace nphase {
 
-// Column tile of a workgroup (one thread per column) and planes per run.  Rows of 64 (FP64)
-// or 32 (FP32) nodes keep the x-shifted pushes of a wave on few partial cache lines; FP32
-// uses the narrower rows so that the Model B pair fractions still fit its LDS budget.  The
-// tile is twice as tall (512 threads, one workgroup of 8 waves per CU, the waves of two
-// 256-thread ones) where the phi and tensor rings of NS evolved sets then fit 160 KB: less
-// x,y halo recomputed per column (measured on 256^3: FP64 2.5 % (Model B) to 6 % (Model A),
-// FP32 1.3 % to 6 %).
+// Column tile of a workgroup (one thread per column) and planes per run.  Rows of 32 nodes
+// (FP32, and FP64 with up to four evolved sets) or 64 (FP64 with five or more, where the
+// 32-wide tile spills more and measured slower); FP32 uses the narrower rows so that the
+// Model B pair fractions still fit its LDS budget.  The tile is twice as tall (512 threads,
+// one workgroup of 8 waves per CU, the waves of two 256-thread ones) where the phi and
+// tensor rings of NS evolved sets then fit 160 KB: less x,y halo recomputed per column
+// (measured on 256^3: FP64 2.5 % (Model B) to 6 % (Model A), FP32 1.3 % to 6 %).  FP64 32 x 16
+// against 64 x 8: 1.5 % on the 256^3 N = 4 step (less halo: 1.41 region and 1.20 inner nodes
+// per column instead of 1.59 and 1.29).
 template <typename T, int NS>
 struct Z3Tile {
-  static constexpr int TX = sizeof(T) == 8 ? 64 : 32;
+  static constexpr int TX = (sizeof(T) == 8 && NS > 4) ? 64 : 32;
   static constexpr int TY0 = 256 / TX, PHR_ = sizeof(T) == 4 ? 4 : 3;
   static constexpr size_t LDS8 = sizeof(T) * (NS * PHR_ * (TX + 4) * (2 * TY0 + 4) +
                                               3 * 3 * (TX + 2) * (2 * TY0 + 2));
@@ -289,6 +291,13 @@ __global__ void __launch_bounds__((Z3Tile<T, (SA ? N : N - 1)>::NT), 2)
   __shared__ T s_phi[NS][PHR][RP];
   __shared__ T s_pf[PF_LDS ? NP : 1][PF_LDS ? 3 : 1][PF_LDS ? RP : 1];
   __shared__ T s_w[3][WR][IP];
+  // FP64: the own column's R_p (Sec. 2.1 sources) of the plane between its S2 and its S3,
+  // one iteration apart, kept in a per-thread LDS slot where it fits beside the rings
+  // instead of registers (it would be live through both stages: 256 VGPRs with 132 B per
+  // lane spilled -> 64 B; 3.5 % on the 256^3 N = 4 step; FP32 does not spill, gains nothing)
+  constexpr bool RLDS = !DEV && (sizeof(T) * (NS * PHR * RP + 3 * WR * IP + NS * D * ZT::NT) +
+                                     (PF_LDS ? PFB : 0) <= 163840);
+  __shared__ T s_rc[RLDS ? NS * D : 1][RLDS ? ZT::NT : 1];
 
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const long long V = a.V;
@@ -550,8 +559,9 @@ __global__ void __launch_bounds__((Z3Tile<T, (SA ? N : N - 1)>::NT), 2)
       Fsc[d] = Fsn[d];
       grc[d] = grn[d];
       mpc[d] = mpn[d];
+      if constexpr (!RLDS)
 #pragma unroll
-      for (int p = 0; p < NS; ++p) Rc[p][d] = Rn[p][d];
+        for (int p = 0; p < NS; ++p) Rc[p][d] = Rn[p][d];
     }
     // S2 (planes z0-1 .. zend)
     if (zs2 >= z0 - 1 && zs2 <= zend) {
@@ -583,11 +593,27 @@ __global__ void __launch_bounds__((Z3Tile<T, (SA ? N : N - 1)>::NT), 2)
         for (int p = 0; p < N; ++p)
 #pragma unroll
           for (int d = 0; d < D; ++d) Fsn[d] += mu_phi[p] * G[p][d];
+        if constexpr (RLDS) {
+          // the slot still holds plane zs3's R (written one iteration ago): take it for S3
 #pragma unroll
-        for (int p = 0; p < NS; ++p)
+          for (int p = 0; p < NS; ++p)
 #pragma unroll
-          for (int d = 0; d < D; ++d) Rn[p][d] = R[p][d];
+            for (int d = 0; d < D; ++d) {
+              Rc[p][d] = s_rc[p * D + d][t];
+              s_rc[p * D + d][t] = R[p][d];
+            }
+        } else {
+#pragma unroll
+          for (int p = 0; p < NS; ++p)
+#pragma unroll
+            for (int d = 0; d < D; ++d) Rn[p][d] = R[p][d];
+        }
       }
+    } else if constexpr (RLDS) {
+#pragma unroll
+      for (int p = 0; p < NS; ++p)
+#pragma unroll
+        for (int d = 0; d < D; ++d) Rc[p][d] = s_rc[p * D + d][t];
     }
     __syncthreads();
     // S3 (planes z0 .. zend-1)

@@ -249,6 +249,31 @@ def test_z_run_length_does_not_change_results(precision, walls, monkeypatch):
     torch.cuda.synchronize()
 
 
+_LONG_RUN_CASES = [(N, sa, ("A", "B", "BC")[(N + 2 * sa) % 3]) for N in range(2, 9)
+                   for sa in (False, True)]
+
+
+@pytest.mark.parametrize("N,solve_all,model", _LONG_RUN_CASES)
+def test_long_z_runs_every_phase_count(N, solve_all, model, monkeypatch):
+    """Every D3Q19 instantiation (N = 2 .. 8, with and without solve-all, the three kinds of
+    phase sources in turn) marching one run over all 41 planes (a handle created for 4
+    compute units) against the oracle: the plane rings, the carried per-column results and
+    the column tiles of each instantiation over a long march, not only runs of one plane."""
+    import torch
+    from _helpers import ragged_spheres
+    cfg, phi = ragged_spheres(33, 27, 41, N=N, model=model[0], solve_all=solve_all)
+    if model == "BC":
+        cfg = dict(cfg, pair_normals="chain")
+    monkeypatch.setenv("NPHASE_CU_COUNT", "4")
+    g = run_gpu(cfg, phi, 8)
+    monkeypatch.delenv("NPHASE_CU_COUNT")
+    o = run_oracle(cfg, phi, 8)
+    e = errors(g, o)
+    print(f"  N={N} solve_all={solve_all} {model}: dphi={e[0]:.2e} du={e[1]:.2e} dP={e[2]:.2e}")
+    assert max(e) <= 1e-12
+    torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("lattice", ["D2Q9", "D3Q19"])
 def test_step_captured_by_the_caller(lattice):
     """A caller may capture nphase_lbm_step into its own graph on the handle's stream: the
