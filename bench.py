@@ -70,8 +70,10 @@ def moments_buffer_bytes_per_node(NS, tsize):
 STEP_SOURCES = ("lattice.hpp", "step_kernel.hpp", "step3d_kernel.hpp", "aux_kernels.hpp",
                 "dispatch.hpp", "kernels_tu.inc", "kernels_f64_d2q9.hip",
                 "kernels_f32_d2q9.hip", "kernels_f64_d3q19_n2to4.hip",
-                "kernels_f64_d3q19_n5to6.hip", "kernels_f64_d3q19_n7to8.hip",
-                "kernels_f32_d3q19_n2to5.hip", "kernels_f32_d3q19_n6to8.hip")
+                "kernels_f64_d3q19_n5.hip", "kernels_f64_d3q19_n6.hip",
+                "kernels_f64_d3q19_n7.hip", "kernels_f64_d3q19_n8.hip",
+                "kernels_f32_d3q19_n2to5.hip", "kernels_f32_d3q19_n6.hip",
+                "kernels_f32_d3q19_n7to8.hip")
 
 
 def kernel_source_hash():

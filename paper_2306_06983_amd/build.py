@@ -16,10 +16,11 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnphase_lbm.so")
 # the D3Q19 step units are split by phase count: the longest unit sets the build time
-SOURCES = ["kernels_f64_d3q19_n7to8.hip", "kernels_f64_d3q19_n5to6.hip",
-           "kernels_f32_d3q19_n6to8.hip", "kernels_f64_d3q19_n2to4.hip",
-           "kernels_f32_d3q19_n2to5.hip", "kernels_f64_d2q9.hip", "kernels_f32_d2q9.hip",
-           "adjoint_d3q19.hip", "adjoint_d2q9.hip", "nphase_lbm.hip"]
+SOURCES = ["kernels_f64_d3q19_n5.hip", "kernels_f64_d3q19_n6.hip", "kernels_f64_d3q19_n7.hip",
+           "kernels_f64_d3q19_n8.hip", "kernels_f32_d3q19_n7to8.hip",
+           "kernels_f32_d3q19_n2to5.hip", "kernels_f64_d3q19_n2to4.hip",
+           "kernels_f64_d2q9.hip", "kernels_f32_d2q9.hip", "adjoint_d3q19.hip",
+           "kernels_f32_d3q19_n6.hip", "adjoint_d2q9.hip", "nphase_lbm.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # no packed-FP32 instructions in any HIP code

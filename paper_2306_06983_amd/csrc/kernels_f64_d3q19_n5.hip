@@ -1,0 +1,6 @@
+// Fused-step kernels: double, D3Q19, phase count 5.
+#define NPHASE_T double
+#define NPHASE_LAT LAT_D3Q19
+#define NPHASE_N_LO 5
+#define NPHASE_N_HI 5
+#include "kernels_tu.inc"

@@ -1,6 +1,6 @@
-// Fused-step kernels: double, D3Q19, phase counts 7 .. 8.
+// Fused-step kernels: double, D3Q19, phase count 7.
 #define NPHASE_T double
 #define NPHASE_LAT LAT_D3Q19
 #define NPHASE_N_LO 7
-#define NPHASE_N_HI 8
+#define NPHASE_N_HI 7
 #include "kernels_tu.inc"

@@ -42,6 +42,7 @@ struct nphase_lbm_s {
   double rho_bar = 0.0;
   int ntx = 0, nty = 0, ntz = 0, ntiles = 0;
   int cus = 256;   // compute units of the device
+  int streamed = 0;   // D3Q19: the state exceeds the last-level cache (streaming access)
   bool inited = false;
   bool failed = false;
   std::string err;
@@ -63,6 +64,10 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 struct Layout {
   size_t f, g, u, mm, mo, partial, mass, flag, total;
 };
+
+// Last-level (Infinity) cache of the device: a state larger than this is streamed by the
+// D3Q19 collide-and-stream pass (non-temporal access to what it touches once per step)
+constexpr size_t LLC_BYTES = size_t(256) << 20;
 
 // sizes of every buffer for a validated parameter set
 Layout layout_of(const nphase_lbm_params& p) {
@@ -204,6 +209,7 @@ void fill_args(nphase_lbm_t h, StepArgs<T>* out) {
     a.ntz = h->ntz;
     a.ntiles = h->ntiles;
     a.cus = h->cus;
+    a.nt = h->streamed;
     a.zr = Z3_ZR;
     a.V = h->V;
     a.model_a_n = p.model_a_n;
@@ -370,6 +376,18 @@ int nphase_lbm_create(const nphase_lbm_params* params, void* workspace_dev, size
   if (const char* env = std::getenv("NPHASE_CU_COUNT")) {
     const int v = std::atoi(env);
     if (v > 0) h->cus = v;
+  }
+  // streaming (non-temporal) access in the D3Q19 collide-and-stream pass for a state
+  // larger than the last-level cache; NPHASE_LLC_BYTES sets another cache size (tests use
+  // 0 to take the streaming code on small grids)
+  {
+    double llc = (double)LLC_BYTES;
+    if (const char* env = std::getenv("NPHASE_LLC_BYTES")) {
+      char* end = nullptr;
+      const double v = std::strtod(env, &end);
+      if (end != env && v >= 0.0) llc = v;
+    }
+    h->streamed = (double)L.total > llc ? 1 : 0;
   }
   h->ws = (char*)workspace_dev;
   h->ws_bytes = ws_bytes;

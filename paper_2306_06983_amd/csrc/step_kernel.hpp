@@ -77,6 +77,8 @@ struct StepArgs {
   int ntx, nty, ntz, ntiles;
   int zr;            // D3Q19: planes per workgroup run of the z-marching passes
   int cus;           // compute units of the device (the z-run length is chosen for them)
+  int nt;            // D3Q19: the state exceeds the last-level cache: the collide-and-stream
+                     // pass streams what it touches once per step (non-temporal access)
   long long V;
   int model_a_n;
   T rho[MAXN];

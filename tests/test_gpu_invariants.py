@@ -249,6 +249,33 @@ def test_z_run_length_does_not_change_results(precision, walls, monkeypatch):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("walls", [False, True])
+def test_streaming_access_does_not_change_results(precision, walls, monkeypatch):
+    """A state larger than the last-level cache takes the D3Q19 pass with non-temporal
+    access; a handle told that the cache holds 0 bytes takes it on a small grid, bitwise
+    equal to the plain pass (and, with long z-runs too, to the oracle in FP64)."""
+    import torch
+    from _helpers import ragged_spheres
+    cfg, phi = ragged_spheres(25, 19, 37, N=4)
+    if walls:
+        cfg = dict(cfg, walls=True, contact_cos=[0.3, -0.2, 0.4])
+    plain = run_gpu(cfg, phi, 12, precision)
+    monkeypatch.setenv("NPHASE_LLC_BYTES", "0")
+    streamed = run_gpu(cfg, phi, 12, precision)
+    monkeypatch.setenv("NPHASE_CU_COUNT", "4")
+    streamed_long = run_gpu(cfg, phi, 12, precision)
+    monkeypatch.delenv("NPHASE_CU_COUNT")
+    monkeypatch.delenv("NPHASE_LLC_BYTES")
+    for k in ("phi", "u", "P"):
+        assert np.array_equal(plain[k], streamed[k]), k
+        assert np.array_equal(plain[k], streamed_long[k]), k
+    if precision == "fp64":
+        o = run_oracle(cfg, phi, 12)
+        assert max(errors(streamed_long, o)) <= 1e-12
+    torch.cuda.synchronize()
+
+
 _LONG_RUN_CASES = [(N, sa, ("A", "B", "BC")[(N + 2 * sa) % 3]) for N in range(2, 9)
                    for sa in (False, True)]
 
@@ -258,15 +285,19 @@ def test_long_z_runs_every_phase_count(N, solve_all, model, monkeypatch):
     """Every D3Q19 instantiation (N = 2 .. 8, with and without solve-all, the three kinds of
     phase sources in turn) marching one run over all 41 planes (a handle created for 4
     compute units) against the oracle: the plane rings, the carried per-column results and
-    the column tiles of each instantiation over a long march, not only runs of one plane."""
+    the column tiles of each instantiation over a long march, not only runs of one plane;
+    odd N with the streaming access of states larger than the last-level cache."""
     import torch
     from _helpers import ragged_spheres
     cfg, phi = ragged_spheres(33, 27, 41, N=N, model=model[0], solve_all=solve_all)
     if model == "BC":
         cfg = dict(cfg, pair_normals="chain")
     monkeypatch.setenv("NPHASE_CU_COUNT", "4")
+    if N % 2:   # odd phase counts take the streaming (non-temporal) form of the pass
+        monkeypatch.setenv("NPHASE_LLC_BYTES", "0")
     g = run_gpu(cfg, phi, 8)
     monkeypatch.delenv("NPHASE_CU_COUNT")
+    monkeypatch.delenv("NPHASE_LLC_BYTES", raising=False)
     o = run_oracle(cfg, phi, 8)
     e = errors(g, o)
     print(f"  N={N} solve_all={solve_all} {model}: dphi={e[0]:.2e} du={e[1]:.2e} dP={e[2]:.2e}")
