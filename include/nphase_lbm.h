@@ -132,9 +132,10 @@ int nphase_lbm_workspace_bytes(const nphase_lbm_params *params, size_t *bytes_ho
  * passes split z into runs whose length is chosen for the device's compute-unit count
  * (read here); the environment variable NPHASE_CU_COUNT, if set to a positive integer,
  * replaces that count (results do not depend on it).  When the state (the workspace
- * bytes) exceeds the 256 MiB last-level cache, the D3Q19 collide-and-stream pass uses
- * non-temporal access for what it touches once per step; NPHASE_LLC_BYTES, if set to a
- * number >= 0, replaces that cache size (results do not depend on it either). */
+ * bytes) exceeds the 256 MiB last-level cache, the D3Q19 collide-and-stream pass and the
+ * FP32 D2Q9 step use non-temporal access for what they touch once per step;
+ * NPHASE_LLC_BYTES, if set to a number >= 0, replaces that cache size (results do not
+ * depend on it either). */
 int nphase_lbm_create(const nphase_lbm_params *params, void *workspace_dev, size_t ws_bytes,
                       void *hip_stream, nphase_lbm_t *out_host);
 

@@ -66,7 +66,8 @@ struct Layout {
 };
 
 // Last-level (Infinity) cache of the device: a state larger than this is streamed by the
-// D3Q19 collide-and-stream pass (non-temporal access to what it touches once per step)
+// D3Q19 collide-and-stream pass and the FP32 D2Q9 step (non-temporal access to what they
+// touch once per step)
 constexpr size_t LLC_BYTES = size_t(256) << 20;
 
 // sizes of every buffer for a validated parameter set
@@ -377,8 +378,8 @@ int nphase_lbm_create(const nphase_lbm_params* params, void* workspace_dev, size
     const int v = std::atoi(env);
     if (v > 0) h->cus = v;
   }
-  // streaming (non-temporal) access in the D3Q19 collide-and-stream pass for a state
-  // larger than the last-level cache; NPHASE_LLC_BYTES sets another cache size (tests use
+  // streaming (non-temporal) access in the D3Q19 collide-and-stream pass and the FP32
+  // D2Q9 step for a state larger than the last-level cache; NPHASE_LLC_BYTES sets another cache size (tests use
   // 0 to take the streaming code on small grids)
   {
     double llc = (double)LLC_BYTES;

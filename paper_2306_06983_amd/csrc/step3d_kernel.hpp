@@ -259,7 +259,14 @@ __global__ void __launch_bounds__(M3_NT, sizeof(T) == 4 ? 4 : 2) nphase_moments3
   }
 }
 
-template <typename T, int N, bool SA, int MODEL, int MODE>
+// NTS: every store of the pass, and the loads of values read once per step (the own
+// node's g, phi^{t-1}, m_phi^{t-1}, j_p), are non-temporal; the host takes it when the state
+// exceeds the last-level cache: those accesses then pass the caches by, which keeps them
+// for the phi and u planes that neighbouring columns read again (256^3 N = 4: FP64 4.72 ->
+// 4.50 ms, FP32 2.65 -> 2.58 ms).  A state that fits the cache keeps plain access (the next
+// pass reads it from there: 64^3 lost 9-15 % to streaming).  A kernel of its own, not a
+// branch inside one, which the compiler may fold into one plain access.
+template <typename T, int N, bool SA, int MODEL, int MODE, bool NTS = false>
 __global__ void __launch_bounds__((Z3Tile<T, (SA ? N : N - 1)>::NT), 2)
     nphase_step3d_kernel(const StepArgs<T> a) {
   using L = Lattice<LAT_D3Q19>;
@@ -540,18 +547,9 @@ __global__ void __launch_bounds__((Z3Tile<T, (SA ? N : N - 1)>::NT), 2)
   T Fsc[D], grc[D], Rc[NS][D], mpc[D];   // current (plane zs3)
 
   // the march, compiled with and without the wall branches (walls before z = 0 and after
-  // z = nz - 1), so that periodic boxes run the plain code, and with and without streaming
-  // access
-  auto march = [&](auto wall, auto streamed) __attribute__((always_inline)) {
+  // z = nz - 1), so that periodic boxes run the plain code
+  auto march = [&](auto wall) __attribute__((always_inline)) {
   constexpr bool W = decltype(wall)::value;
-  // Every store of the pass, and the loads of values read once per step (the own node's
-  // g, phi^{t-1}, m_phi^{t-1}, j_p), are non-temporal when the state exceeds the last-level
-  // cache: they then pass the caches by, which keeps them for the phi and u planes that
-  // neighbouring columns read again (256^3 N = 4: FP64 4.72 -> 4.47 ms, FP32 2.65 -> 2.57
-  // ms).  A state that fits the cache keeps plain access (the next pass reads it from there:
-  // 64^3 lost 9-15 % to streaming).  A compile-time choice: a run-time select between the
-  // two forms is folded into one plain access.
-  constexpr bool NTS = decltype(streamed)::value;
   auto ST = [&](T* base, int comp, unsigned node, T v) {
     T* ptr = &(base + (size_t)comp * Vs)[node];
     if constexpr (NTS) __builtin_nontemporal_store(v, ptr);
@@ -861,18 +859,8 @@ __global__ void __launch_bounds__((Z3Tile<T, (SA ? N : N - 1)>::NT), 2)
     }
   }
   };
-  // (the fields pass, run once per read-back, keeps plain access)
-  auto run = [&](auto wall) __attribute__((always_inline)) {
-    if constexpr (MODE == MODE_STEP) {
-      if (a.nt) {
-        march(wall, std::true_type{});
-        return;
-      }
-    }
-    march(wall, std::false_type{});
-  };
-  if (a.walls) run(std::true_type{});
-  else run(std::false_type{});
+  if (a.walls) march(std::true_type{});
+  else march(std::false_type{});
 }
 
 // ---- moment-representation state outside the step ----------------------------------------

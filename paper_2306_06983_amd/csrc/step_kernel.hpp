@@ -77,8 +77,8 @@ struct StepArgs {
   int ntx, nty, ntz, ntiles;
   int zr;            // D3Q19: planes per workgroup run of the z-marching passes
   int cus;           // compute units of the device (the z-run length is chosen for them)
-  int nt;            // D3Q19: the state exceeds the last-level cache: the collide-and-stream
-                     // pass streams what it touches once per step (non-temporal access)
+  int nt;            // the state exceeds the last-level cache: the D3Q19 collide-and-stream
+                     // pass and the FP32 D2Q9 step stream what they touch once per step
   long long V;
   int model_a_n;
   T rho[MAXN];
@@ -329,7 +329,12 @@ __device__ __forceinline__ T pair_fraction_fast(T pp, T pq) {
   }
 }
 
-template <typename T, int LAT, int N, bool SA, int MODEL, int MODE>
+// NTS: stage 3 stores everything, and loads the own node's g and m_phi^{t-1},
+// non-temporally; the host takes it for an FP32 state larger than the last-level cache
+// (2048^2 N = 5: 0.468 -> 0.443 ms; FP64 gains nothing there).  A kernel of its own, not a
+// branch inside one: the compiler merges the two forms of each access of a branch into one
+// plain access.
+template <typename T, int LAT, int N, bool SA, int MODEL, int MODE, bool NTS = false>
 __global__ void __launch_bounds__((StepTile<T, LAT, N, SA, MODEL>::NT),
                                   (StepTile<T, LAT, N, SA, MODEL>::MINW))
     nphase_step_kernel(const StepArgs<T> a) {
@@ -394,7 +399,7 @@ __global__ void __launch_bounds__((StepTile<T, LAT, N, SA, MODEL>::NT),
   auto LD = [&](const T* base, int comp, unsigned node) -> T {
     return (base + (size_t)comp * Vs)[node];
   };
-  auto ST = [&](T* base, int comp, unsigned node, T v) { (base + (size_t)comp * Vs)[node] = v; };
+
 
   auto region_gidx = [&](int rx, int ry, int rz) -> long long {
     const int gx = wrap(tx0 - 2 + rx, nx);
@@ -766,6 +771,16 @@ __global__ void __launch_bounds__((StepTile<T, LAT, N, SA, MODEL>::NT),
   if (!valid) return;
 
   // ---------------------------------------------------------------- stage 3
+  auto ST = [&](T* base, int comp, unsigned node, T v) {
+    T* ptr = &(base + (size_t)comp * Vs)[node];
+    if constexpr (NTS) __builtin_nontemporal_store(v, ptr);
+    else *ptr = v;
+  };
+  auto LD1 = [&](const T* base, int comp, unsigned node) -> T {
+    const T* ptr = &(base + (size_t)comp * Vs)[node];
+    if constexpr (NTS) return __builtin_nontemporal_load(ptr);
+    else return *ptr;
+  };
   const T* phi_own = phc;   // phi of all N phases at the own node
   // correction force F_c,b = -1/2 sum_a D_a A_ab
   T Fc[D];
@@ -834,7 +849,7 @@ __global__ void __launch_bounds__((StepTile<T, LAT, N, SA, MODEL>::NT),
   T gv[Q];
   gv[0] = T(0);
 #pragma unroll
-  for (int i = 1; i < Q; ++i) gv[i] = LD(a.g_src, i - 1, (unsigned)g_own);
+  for (int i = 1; i < Q; ++i) gv[i] = LD1(a.g_src, i - 1, (unsigned)g_own);
   T jg[D], Pi[D][D], sumg = T(0);
 #pragma unroll
   for (int d = 0; d < D; ++d) {
@@ -862,7 +877,7 @@ __global__ void __launch_bounds__((StepTile<T, LAT, N, SA, MODEL>::NT),
     u[d] = (jg[d] + T(0.5) * F[d]) * inv_rho;
     m[d] = rho * u[d] + mphi[d];
     um[d] = LD(a.u_src, d, (unsigned)g_own);
-    mm_prev[d] = LD(a.mm, d, (unsigned)g_own);
+    mm_prev[d] = LD1(a.mm, d, (unsigned)g_own);
   }
   T phm[N];
 #pragma unroll

@@ -251,13 +251,18 @@ def test_z_run_length_does_not_change_results(precision, walls, monkeypatch):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("walls", [False, True])
-def test_streaming_access_does_not_change_results(precision, walls, monkeypatch):
-    """A state larger than the last-level cache takes the D3Q19 pass with non-temporal
-    access; a handle told that the cache holds 0 bytes takes it on a small grid, bitwise
-    equal to the plain pass (and, with long z-runs too, to the oracle in FP64)."""
+@pytest.mark.parametrize("lattice", ["D2Q9", "D3Q19"])
+def test_streaming_access_does_not_change_results(lattice, precision, walls, monkeypatch):
+    """A state larger than the last-level cache takes the D3Q19 pass (and the FP32 D2Q9
+    step) with non-temporal access; a handle told that the cache holds 0 bytes takes it on
+    a small grid, bitwise equal to the plain pass (and, with long z-runs too, to the oracle
+    in FP64)."""
     import torch
-    from _helpers import ragged_spheres
-    cfg, phi = ragged_spheres(25, 19, 37, N=4)
+    from _helpers import ragged_discs, ragged_spheres
+    if lattice == "D3Q19":
+        cfg, phi = ragged_spheres(25, 19, 37, N=4)
+    else:
+        cfg, phi = ragged_discs(50, 37, N=4, count=4, rmin=3.0, rmax=4.5)
     if walls:
         cfg = dict(cfg, walls=True, contact_cos=[0.3, -0.2, 0.4])
     plain = run_gpu(cfg, phi, 12, precision)
