@@ -402,7 +402,8 @@ __global__ void __launch_bounds__((Z3Tile<T, (SA ? N : N - 1)>::NT), 2)
 #pragma unroll
       for (int p = 0; p < N; ++p)
 #pragma unroll
-        for (int q = p + 1; q < N; ++q, ++k) s_pf[k][ring_of(z, 3)][r] = pair_fraction(ph[p], ph[q]);
+        for (int q = p + 1; q < N; ++q, ++k)
+          s_pf[k][ring_of(z, 3)][r] = pair_fraction_fast(ph[p], ph[q]);
     }
   };
   auto s1_plane = [&](int z, auto wall) __attribute__((always_inline)) {

@@ -308,9 +308,11 @@ __device__ __forceinline__ T pair_fraction(T pp, T pq) {
   return (s > T(PAIR_EPS)) ? pp / s : T(0.5);
 }
 
-// The same fraction with the quotient from the hardware reciprocal estimate refined by two
-// Newton-Raphson steps and one residual correction (FP64; within an ulp of pp / s), for
-// the stencils that recompute the fractions of every neighbour
+// The same fraction with the quotient from the hardware reciprocal estimate, refined by two
+// Newton-Raphson steps and one residual correction in FP64 (within an ulp of pp / s) and by
+// one residual correction in FP32, in place of the IEEE division sequence: 11 -> 7 FP64
+// instructions (256^3 N = 4 FP64 step 5.66 -> 5.44 ms where every stencil point recomputes
+// its fractions), 1.8 % on the FP32 step there, where they are staged once per node
 template <typename T>
 __device__ __forceinline__ T pair_fraction_fast(T pp, T pq) {
   if constexpr (sizeof(T) == 8) {
@@ -325,7 +327,12 @@ __device__ __forceinline__ T pair_fraction_fast(T pp, T pq) {
     q = __builtin_fma(r, __builtin_fma(-s, q, pp), q);
     return s > PAIR_EPS ? q : 0.5;
   } else {
-    return pair_fraction(pp, pq);
+    // FP32: the reciprocal estimate (1 ulp) and one residual correction
+    const float s = pp + pq;
+    const float r = __builtin_amdgcn_rcpf(s);
+    float q = pp * r;
+    q = __builtin_fmaf(r, __builtin_fmaf(-s, q, pp), q);
+    return s > float(PAIR_EPS) ? q : 0.5f;
   }
 }
 
@@ -582,7 +589,7 @@ __global__ void __launch_bounds__((StepTile<T, LAT, N, SA, MODEL>::NT),
 #pragma unroll
       for (int p = 0; p < N; ++p)
 #pragma unroll
-        for (int q = p + 1; q < N; ++q, ++k) s_pf[k][r] = pair_fraction(ph[p], ph[q]);
+        for (int q = p + 1; q < N; ++q, ++k) s_pf[k][r] = pair_fraction_fast(ph[p], ph[q]);
     }
   }
   __syncthreads();
@@ -653,7 +660,7 @@ __global__ void __launch_bounds__((StepTile<T, LAT, N, SA, MODEL>::NT),
           for (int q = p + 1; q < N; ++q) {
             T v;
             if constexpr (PF_LDS) v = s_pf[k][r + roff(i)];
-            else v = pair_fraction(ph[p], ph[q]);
+            else v = pair_fraction_fast(ph[p], ph[q]);
 #pragma unroll
             for (int d = 0; d < D; ++d) {
               if (L::c(i, d) == 1) H[k][d] += wg * v;
