@@ -66,8 +66,9 @@ def moments_buffer_bytes_per_node(NS, tsize):
     return 2 * NS * (4 + (1 if tsize == 4 else 0)) * tsize
 
 
-# sources of the timed step kernels (the adjoint and the host code do not enter a step)
-STEP_SOURCES = ("lattice.hpp", "step_kernel.hpp", "step3d_kernel.hpp", "aux_kernels.hpp",
+# sources of the timed step kernels and of the host code that launches them (it chooses
+# tiles, z-runs and the streaming form); the adjoint kernels do not enter a step
+STEP_SOURCES = ("nphase_lbm.hip", "lattice.hpp", "step_kernel.hpp", "step3d_kernel.hpp", "aux_kernels.hpp",
                 "dispatch.hpp", "kernels_tu.inc", "kernels_f64_d2q9.hip",
                 "kernels_f32_d2q9.hip", "kernels_f64_d3q19_n2to4.hip",
                 "kernels_f64_d3q19_n5.hip", "kernels_f64_d3q19_n6.hip",
