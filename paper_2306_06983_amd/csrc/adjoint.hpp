@@ -158,15 +158,15 @@ __global__ void __launch_bounds__(256) adj_fwd1(const AdjArgs a) {
   if (!SA) a.F_phi[(long long)(N - 1) * V + x] = 1.0 - rest;
 }
 
-template <int LAT, int N, bool SA, int MODEL>
-__global__ void __launch_bounds__(256) adj_fwd2(const AdjArgs a) {
-  using L = Lattice<LAT>;
+// G, L, R (and H) and the tensor W at node x from its neighbours: `phi_at(i, ph)` gives the
+// N order parameters at x + c_i (the wetting ghost where that lies behind a wall) and
+// `pf_at(i, k, php, phq)` the pair fraction k there
+template <class L, int N, bool SA, int MODEL, class PhiAt, class PfAt>
+__device__ __forceinline__ void fwd2_node(const AdjArgs& a, long long x, PhiAt&& phi_at,
+                                          PfAt&& pf_at) {
   constexpr int Q = L::Q, D = L::D, NP = N * (N - 1) / 2;
   constexpr int NW = (D == 3) ? 3 : 1;
-  const long long x = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (x >= a.V) return;
   const long long V = a.V;
-  Nbr<L> nb(x, a.nx, a.ny, a.nz, a.walls);
   double phc[N], G[N][D], Lp[N], R[N][D], H[NP > 0 ? NP : 1][D];
   for (int p = 0; p < N; ++p) {
     phc[p] = a.F_phi[(long long)p * V + x];
@@ -179,14 +179,7 @@ __global__ void __launch_bounds__(256) adj_fwd2(const AdjArgs a) {
   for (int i = 1; i < Q; ++i) {
     const double wg = 3.0 * L::w(i), wl = 6.0 * L::w(i);
     double ph[N];
-    if (nb.cross(i, 1)) {
-      // ghost behind the wall: the wetting condition of the facing fluid node
-      double pf[N];
-      phases_at<N>(a, nb.facing(i, 1), pf);
-      wetting_ghost<double, N>(a, pf, ph);
-    } else {
-      phases_at<N>(a, nb.at(i, 1), ph);
-    }
+    phi_at(i, ph);
     for (int p = 0; p < N; ++p) {
       for (int d = 0; d < D; ++d) G[p][d] += wg * (double)L::c(i, d) * ph[p];
       Lp[p] += wl * (ph[p] - phc[p]);
@@ -195,7 +188,7 @@ __global__ void __launch_bounds__(256) adj_fwd2(const AdjArgs a) {
       int k = 0;
       for (int p = 0; p < N; ++p)
         for (int q = p + 1; q < N; ++q, ++k) {
-          const double v = pair_fraction(ph[p], ph[q]);
+          const double v = pf_at(i, k, ph[p], ph[q]);
           for (int d = 0; d < D; ++d) H[k][d] += wg * (double)L::c(i, d) * v;
         }
     }
@@ -264,6 +257,90 @@ __global__ void __launch_bounds__(256) adj_fwd2(const AdjArgs a) {
     W[2] = mphi[1] * u[2] - u[1] * mphi[2];
   }
   for (int k = 0; k < NW; ++k) a.F_W[(long long)k * V + x] = W[k];
+}
+
+
+// one node per thread; the neighbours' order parameters are read from memory
+template <int LAT, int N, bool SA, int MODEL>
+__global__ void __launch_bounds__(256) adj_fwd2(const AdjArgs a) {
+  using L = Lattice<LAT>;
+  const long long x = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (x >= a.V) return;
+  const Nbr<L> nb(x, a.nx, a.ny, a.nz, a.walls);
+  fwd2_node<L, N, SA, MODEL>(
+      a, x,
+      [&](int i, double* ph) {
+        if (nb.cross(i, 1)) {
+          // ghost behind the wall: the wetting condition of the facing fluid node
+          double pf[N];
+          phases_at<N>(a, nb.facing(i, 1), pf);
+          wetting_ghost<double, N>(a, pf, ph);
+        } else {
+          phases_at<N>(a, nb.at(i, 1), ph);
+        }
+      },
+      [&](int, int, double php, double phq) { return pair_fraction(php, phq); });
+}
+
+// D2Q9 with a 32 x 8 tile: the order parameters of the tile and its 1-node ring (the
+// wetting ghosts in the rows behind a wall) and, for Model B, their pair fractions staged
+// in LDS once per workgroup, instead of read and divided again by every neighbour
+constexpr int F2_TX = 32, F2_TY = 8;
+template <int N, int MODEL>
+constexpr int fwd2_fields() { return N + (MODEL == MODEL_B ? N * (N - 1) / 2 : 0); }
+template <int N, int MODEL>
+constexpr bool fwd2_tiled() {
+  return fwd2_fields<N, MODEL>() * (F2_TX + 2) * (F2_TY + 2) * 8 <= 65536;
+}
+template <int N, bool SA, int MODEL>
+__global__ void __launch_bounds__(F2_TX * F2_TY) adj_fwd2_tile(const AdjArgs a) {
+  using L = Lattice<LAT_D2Q9>;
+  constexpr int NP = N * (N - 1) / 2;
+  constexpr int RX = F2_TX + 2, RY = F2_TY + 2, RP = RX * RY;
+  __shared__ double s_ph[N][RP];
+  __shared__ double s_pf[MODEL == MODEL_B ? NP : 1][RP];
+  const int nx = a.nx, ny = a.ny;
+  const int ntx = (nx + F2_TX - 1) / F2_TX;
+  const int tile = xcd_block(blockIdx.x, gridDim.x);
+  const int tx0 = (tile % ntx) * F2_TX, ty0 = (tile / ntx) * F2_TY;
+  const long long V = a.V;
+  for (int r = threadIdx.x; r < RP; r += F2_TX * F2_TY) {
+    const int gx = wrap(tx0 - 1 + r % RX, nx), gy = ty0 - 1 + r / RX;
+    double ph[N];
+    if (a.walls && (gy == -1 || gy == ny)) {
+      // the row behind a wall: the wetting ghost of the facing fluid row
+      double pf[N];
+      phases_at<N>(a, (long long)gx + (long long)nx * (gy < 0 ? 0 : ny - 1), pf);
+      wetting_ghost<double, N>(a, pf, ph);
+    } else {
+      phases_at<N>(a, (long long)gx + (long long)nx * wrap(gy, ny), ph);
+    }
+#pragma unroll
+    for (int p = 0; p < N; ++p) s_ph[p][r] = ph[p];
+    if constexpr (MODEL == MODEL_B) {
+      int k = 0;
+#pragma unroll
+      for (int p = 0; p < N; ++p)
+#pragma unroll
+        for (int q = p + 1; q < N; ++q, ++k) s_pf[k][r] = pair_fraction(ph[p], ph[q]);
+    }
+  }
+  __syncthreads();
+  const int lx = threadIdx.x % F2_TX, ly = threadIdx.x / F2_TX;
+  if (tx0 + lx >= nx || ty0 + ly >= ny) return;
+  const long long x = (long long)(tx0 + lx) + (long long)nx * (ty0 + ly);
+  const int rx = (lx + 1) + RX * (ly + 1);
+  (void)V;
+  fwd2_node<L, N, SA, MODEL>(
+      a, x,
+      [&](int i, double* ph) {
+        const int r = rx + L::c(i, 0) + RX * L::c(i, 1);
+#pragma unroll
+        for (int p = 0; p < N; ++p) ph[p] = s_ph[p][r];
+      },
+      [&](int i, int k, double, double) {
+        return s_pf[k][rx + L::c(i, 0) + RX * L::c(i, 1)];
+      });
 }
 
 template <int LAT>
