@@ -29,3 +29,17 @@ def test_bytes_per_node_update():
     assert bench.algorithmic_bytes_per_node_moment_form(3, 19, 3, 4) == 384
     assert bench.moments_buffer_bytes_per_node(3, 8) == 192
     assert bench.moments_buffer_bytes_per_node(3, 4) == 120
+
+
+def test_kernel_hash_covers_every_step_unit():
+    """The traffic counters are used only while the sources they were taken with are
+    unchanged: every step translation unit the build compiles, the headers they include and
+    the host code that launches them enter the hash."""
+    from paper_2306_06983_amd import build
+    step_units = {s for s in build.SOURCES if s.startswith("kernels_")} | {"nphase_lbm.hip"}
+    assert step_units <= set(bench.STEP_SOURCES)
+    csrc = os.path.join(ROOT, "paper_2306_06983_amd", "csrc")
+    for inc in ("kernels_tu.inc", "dispatch.hpp", "step_kernel.hpp", "step3d_kernel.hpp",
+                "lattice.hpp", "aux_kernels.hpp"):
+        assert os.path.exists(os.path.join(csrc, inc))
+        assert inc in bench.STEP_SOURCES
