@@ -51,14 +51,19 @@ namespace nphase {
 // tensor rings of NS evolved sets then fit 160 KB: less x,y halo recomputed per column
 // (measured on 256^3: FP64 2.5 % (Model B) to 6 % (Model A), FP32 1.3 % to 6 %).  FP64 32 x 16
 // against 64 x 8: 1.5 % on the 256^3 N = 4 step (less halo: 1.41 region and 1.20 inner nodes
-// per column instead of 1.59 and 1.29).
+// per column instead of 1.59 and 1.29).  FP64 with five or more evolved sets keeps the short
+// 256-thread tile even where the tall one fits: at two waves per SIMD its registers spill
+// 0.6-1.1 KB per lane to scratch, at one wave per SIMD they stay in the accumulation
+// registers (160^3 steps 1-40 % faster; and the N = 6 Model B kernel with 1.1 KB of scratch
+// per lane gave results that differed in the 8th digit from run to run, which the short
+// tile's does not).
 template <typename T, int NS>
 struct Z3Tile {
   static constexpr int TX = (sizeof(T) == 8 && NS > 4) ? 64 : 32;
   static constexpr int TY0 = 256 / TX, PHR_ = sizeof(T) == 4 ? 4 : 3;
   static constexpr size_t LDS8 = sizeof(T) * (NS * PHR_ * (TX + 4) * (2 * TY0 + 4) +
                                               3 * 3 * (TX + 2) * (2 * TY0 + 2));
-  static constexpr bool TALL = LDS8 <= 163840;
+  static constexpr bool TALL = LDS8 <= 163840 && !(sizeof(T) == 8 && NS >= 5);
   static constexpr int TY = TALL ? 2 * TY0 : TY0;
   static constexpr int NT = TX * TY;
   static constexpr int BUDGET = TALL ? 163840 : 81920;   // LDS of one workgroup
