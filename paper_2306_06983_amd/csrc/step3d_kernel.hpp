@@ -152,30 +152,55 @@ __global__ void __launch_bounds__(M3_NT, sizeof(T) == 4 ? 4 : 2) nphase_moments3
   // Plane z of set p (tile + ring) is fetched into registers (PL values per thread) one
   // iteration ahead and written to its ring slot after the compute, so the loads overlap
   // the LDS work.  Positions past a ragged edge (columns no thread owns) wrap like the
-  // rest, so every load stays inside the grid.
-  constexpr int PL = (NF * RP + M3_NT - 1) / M3_NT;
+  // rest, so every load stays inside the grid.  FP64 spreads the NF x RP values evenly over
+  // the threads (a thread's values then belong to different fields); FP32 has each thread
+  // fetch the same PR ring positions of every field, so that a load's field (its base
+  // address) is the same in every lane: the per-lane field offsets otherwise held across
+  // the z loop spill 240 B per lane at the pass's 128-register budget, which this form
+  // does not (256^3 N = 4 FP32 step 2.53 -> 2.44 ms; the same form in FP64, at 2 waves per
+  // SIMD, measured 40 % slower).
+  constexpr bool UNIF = DEV;
+  constexpr int PR = (RP + M3_NT - 1) / M3_NT;   // FP32: ring positions per thread
+  constexpr int PL = UNIF ? NF * PR : (NF * RP + M3_NT - 1) / M3_NT;
+  constexpr int PO = UNIF ? PR : PL;
   T pre[PL];
-  unsigned poff[PL];   // in-plane node of each fetched value (fixed per workgroup)
+  unsigned poff[PO];   // in-plane node of each fetched position (fixed per workgroup)
 #pragma unroll
-  for (int j = 0; j < PL; ++j) {
+  for (int j = 0; j < PO; ++j) {
     const int k = t + j * M3_NT;
-    const int r = (k < NF * RP ? k : 0) % RP;
+    const int r = UNIF ? (k < RP ? k : 0) : (k < NF * RP ? k : 0) % RP;
     poff[j] = (unsigned)wrap(tx0 - 1 + r % RX, nx) + (unsigned)nx * (unsigned)wrap(ty0 - 1 + r / RX, ny);
   }
   auto fetch_plane = [&](int p, int z) {
     const size_t zoff = plane * (size_t)wrap(z, nz);
+    if constexpr (UNIF) {
 #pragma unroll
-    for (int j = 0; j < PL; ++j) {
-      const int k = t + j * M3_NT;
-      if (k < NF * RP) pre[j] = LD(p * NMR + k / RP, (size_t)poff[j] + zoff);
+      for (int c = 0; c < NF; ++c)
+#pragma unroll
+        for (int j = 0; j < PR; ++j)
+          if (t + j * M3_NT < RP) pre[c * PR + j] = LD(p * NMR + c, (size_t)poff[j] + zoff);
+    } else {
+#pragma unroll
+      for (int j = 0; j < PL; ++j) {
+        const int k = t + j * M3_NT;
+        if (k < NF * RP) pre[j] = LD(p * NMR + k / RP, (size_t)poff[j] + zoff);
+      }
     }
   };
   auto store_plane = [&](int z) {
     const int sl = slot(z);
+    if constexpr (UNIF) {
 #pragma unroll
-    for (int j = 0; j < PL; ++j) {
-      const int k = t + j * M3_NT;
-      if (k < NF * RP) s_mr[sl][k / RP][k % RP] = pre[j];
+      for (int c = 0; c < NF; ++c)
+#pragma unroll
+        for (int j = 0; j < PR; ++j)
+          if (t + j * M3_NT < RP) s_mr[sl][c][t + j * M3_NT] = pre[c * PR + j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < PL; ++j) {
+        const int k = t + j * M3_NT;
+        if (k < NF * RP) s_mr[sl][k / RP][k % RP] = pre[j];
+      }
     }
   };
   const int rown = (lx + 1) + RX * (ly + 1);
